@@ -1,0 +1,173 @@
+/*
+ * scocg -- shifted COCG solver for unperturbed Green's-function columns on MI355X.
+ *
+ * The library computes, for one real-symmetric real-space finite-difference
+ * Hamiltonian H of a transition region, the columns
+ *
+ *     x^{(k)}_j = [Z_k - H]^{-1} e_j ,   Z_k = E_k + i*eta ,
+ *
+ * of the unperturbed Green's function (Sec. 3B, Eq. 17), restricted to a set S
+ * of output rows ("the required elements", Appendix after Eq. A12).  One seed
+ * Krylov recurrence per right-hand side e_j serves every energy Z_k: the
+ * shifted COCG method with collinear residuals (Appendix, Eqs. A7-A12) and
+ * seed switching (Eq. A13).
+ *
+ * Operator (Sec. 2A, Eqs. 2-4, with the nonlocal Kleinman-Bylander extension):
+ *     H = H_kin + diag(V) + sum_a P_a diag(D_a) P_a^T
+ * Grid nx*ny*nz, index i = ix + nx*(iy + ny*iz) (each x-y plane contiguous).
+ * H_kin is a symmetric stencil of half-width nf along each axis: periodic in
+ * x and y, truncated in z (the wavefunction vanishes outside planes 0..nz-1,
+ * the finite transition block of Eq. 4):
+ *     (H_kin v)_i = sum_{axis} sum_{k=-nf..nf} coef[axis][|k|] v_{i + k e_axis}.
+ *
+ * Conventions for every entry point:
+ *   - Return value 0 = success.  Negative = error, no results:
+ *       SCOCG_EINVAL (bad shape, index, non-finite input, Im z <= 0),
+ *       SCOCG_ENOMEM (device allocation failed), SCOCG_EHIP (HIP runtime
+ *       error), SCOCG_ENOSOLVE (green_columns before a successful solve).
+ *     Positive = warning with partial results and per-pair status:
+ *       SCOCG_NOT_ALL_CONVERGED, SCOCG_BREAKDOWN.
+ *     scocg_last_error() returns a thread-local message for the last failure.
+ *   - Complex numbers are two doubles (re, im), interleaved.
+ *   - Host arrays passed in are copied during the call; the caller keeps them.
+ *   - A handle is not thread-safe; concurrent calls on one handle race.
+ */
+#ifndef SCOCG_H
+#define SCOCG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SCOCG_OK 0
+#define SCOCG_EINVAL (-1)
+#define SCOCG_ENOMEM (-2)
+#define SCOCG_EHIP (-3)
+#define SCOCG_ENOSOLVE (-4)
+#define SCOCG_NOT_ALL_CONVERGED 1
+#define SCOCG_BREAKDOWN 2
+
+/* precision of the Krylov vectors and of the operator arithmetic */
+#define SCOCG_FP64 0   /* complex128 vectors, FP64 stencil and projectors */
+#define SCOCG_MIXED 1  /* complex64 vectors, FP32 stencil and projectors; every
+                          scalar recurrence, x^{(k)} and the dot accumulation in FP64 */
+
+/* per-pair status */
+#define SCOCG_PAIR_CONVERGED 0
+#define SCOCG_PAIR_MAXITER 1
+#define SCOCG_PAIR_BREAKDOWN 2
+
+/* output element type for scocg_green_columns */
+#define SCOCG_C128 0
+#define SCOCG_C64 1
+
+typedef struct scocg_ctx *scocg_handle;
+
+typedef struct {
+    int64_t nx, ny, nz;  /* grid; nx, ny >= nf; nz >= 1 */
+    int32_t nf;          /* stencil half-width, 1..4 (4 = the 25-point star) */
+    int32_t n_proj;      /* projector channels per atom, 0..4 (0 = no nonlocal part) */
+} scocg_grid;
+
+/*
+ * Create a handle: uploads H to the device once.
+ *   coef      [3][nf+1] host, Ha: H_kin coefficients along x, y, z.
+ *   vloc      [N] host, Ha, local potential (diagonal of H).
+ *   n_atoms   number of projector blocks (0 allowed).
+ *   atom_ptr  [n_atoms+1] host, CSR offsets (atom_ptr[0] = 0, non-decreasing).
+ *   atom_idx  [atom_ptr[n_atoms]] host, grid index of each entry, in [0, N);
+ *             an index may not repeat within one atom.
+ *   atom_P    [entries][n_proj] host, projector values (row per entry).
+ *   atom_D    [n_atoms][n_proj] host, Ha, projector energies.
+ *   precision SCOCG_FP64 or SCOCG_MIXED.
+ *   hip_stream hipStream_t to enqueue on (NULL: the handle creates and owns a
+ *             non-blocking stream of default priority).
+ *   out       receives the handle (freed by scocg_destroy).
+ * The current HIP device at create time is the handle's device.
+ */
+int scocg_create(const scocg_grid *g, const double *coef, const double *vloc,
+                 int32_t n_atoms, const int64_t *atom_ptr, const int64_t *atom_idx,
+                 const double *atom_P, const double *atom_D, int32_t precision,
+                 void *hip_stream, scocg_handle *out);
+
+typedef struct {
+    double tol;          /* stop a pair at ||r^{(k)}|| <= tol (||e_j|| = 1); 0 -> 1e-10 */
+    int64_t max_iter;    /* seed iterations cap; 0 -> 100000 */
+    int32_t init_seed;   /* index of the first seed energy; -1 -> K/2 */
+    int32_t seed_switch; /* 1: switch the seed after it converges (Eq. A13); 0: keep it */
+    int32_t full;        /* 1: S = all N rows (full x^{(k)} kept; enables the true residual) */
+    int32_t refine;      /* SCOCG_MIXED with full = 1: max refinement passes for pairs
+                            whose FP64 true residual misses tol (0 = check only, -1 = skip
+                            the check); ignored for SCOCG_FP64 */
+    int32_t poll_every;  /* seed iterations between host convergence polls; 0 -> auto */
+    int32_t use_graph;   /* 1: replay the per-poll iterations as one captured hipGraph */
+    int32_t timing;      /* 1: bracket every kernel launch with HIP events and report the
+                            summed durations per kernel family (scocg_report.kernel_ms);
+                            launches are then direct (use_graph is ignored) */
+} scocg_solve_opts;
+
+/* kernel families of one seed iteration (index into scocg_report.kernel_ms) */
+#define SCOCG_K_PROJ 0     /* projector contraction C_a = D_a P_a^T r_n */
+#define SCOCG_K_MU 1       /* stencil pass: partials of (r_n, A r_n) */
+#define SCOCG_K_ALPHA 2    /* seed alpha_n, c_n */
+#define SCOCG_K_UPDATE 3   /* stencil pass: r_{n+1} (three-term recurrence) + dot partials */
+#define SCOCG_K_CONTROL 4  /* beta_n, pi recurrences, convergence, compaction, seed switch */
+#define SCOCG_K_SHIFT 5    /* x^(k), p^(k) on the rows S */
+#define SCOCG_K_FAMILIES 6
+
+typedef struct {
+    int64_t *iters;      /* [K*R] host or NULL: seed iteration at which pair (k,j) froze */
+    double *est_resid;   /* [K*R] host or NULL: recursive ||r^{(k)}_j|| at freeze */
+    double *true_resid;  /* [K*R] host or NULL: FP64 ||e_j - (Z_k - H) x|| (NaN if not computed) */
+    int32_t *status;     /* [K*R] host or NULL: SCOCG_PAIR_* */
+    int64_t seed_iters;  /* out: seed iterations run (max over columns) */
+    int64_t n_switches;  /* out: seed switches, summed over columns */
+    int64_t refined;     /* out: pairs that went through refinement */
+    double solve_ms;     /* out: device time of the solve (first kernel to last, HIP events) */
+    int64_t block_iters; /* out: column-block iterations run (sum over blocks of B = columns
+                            per block: 8 for SCOCG_FP64, 16 for SCOCG_MIXED) */
+    int32_t block_width; /* out: B */
+    int32_t n_blocks;    /* out: column blocks */
+    double kernel_ms[SCOCG_K_FAMILIES];      /* out (timing = 1): summed launch durations */
+    int64_t kernel_launches[SCOCG_K_FAMILIES]; /* out (timing = 1): launches timed */
+} scocg_report;
+
+/*
+ * Solve (Z_k - H) x^{(k)}_j = e_{rhs_idx[j]} for all k < K, j < R (Sec. 3B,
+ * Eq. 17; Appendix, Eqs. A7-A13).  Index layout of the report arrays: k*R + j.
+ *   K, z      K >= 1 energies, host [K][2] (re, im), every Im z > 0.
+ *   R, rhs_idx R >= 1 distinct-or-not grid indices in [0, N), host.
+ *   nS, s_idx output rows, host; s_idx = NULL and nS = 0 -> S = rhs set.
+ *             Ignored when opts->full = 1 (S = 0..N-1).
+ *   opts      NULL -> defaults.  rep may be NULL.
+ * Blocks the calling thread until the report is filled (one host
+ * synchronisation per convergence poll).  Results stay on the device until
+ * scocg_green_columns or the next solve.
+ */
+int scocg_solve(scocg_handle h, int32_t K, const double *z, int32_t R, const int64_t *rhs_idx,
+                int32_t nS, const int64_t *s_idx, const scocg_solve_opts *opts,
+                scocg_report *rep);
+
+/*
+ * Copy the last solve's x^{(k)}_j[S] into dst, layout [K][R][nS] (row-major),
+ * element SCOCG_C128 (2 doubles) or SCOCG_C64 (2 floats).  dst is a device
+ * pointer (dst_is_device = 1, on the handle's device) or host memory.
+ * Enqueued on the handle's stream; returns after the copy completes.
+ */
+int scocg_green_columns(scocg_handle h, void *dst, int32_t dtype, int32_t dst_is_device);
+
+/* Apply y = H x for complex128 device vectors x, y of length N (checking aid). */
+int scocg_apply_h(scocg_handle h, const void *x_dev, void *y_dev);
+
+/* Release every device buffer of the handle.  NULL is ignored. */
+void scocg_destroy(scocg_handle h);
+
+/* Thread-local description of the last error ("" if none). */
+const char *scocg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SCOCG_H */

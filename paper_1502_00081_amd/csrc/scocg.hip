@@ -1,0 +1,667 @@
+// Host driver and C ABI of the shifted COCG Green's-function solver (see include/scocg.h).
+//
+// scocg_create uploads H once: the local potential, the stencil coefficients
+// (kernel arguments) and the projector blocks in two CSR forms (by atom for the
+// contraction C_a = P_a^T r, by grid point for the application P_a D_a C_a).
+// scocg_solve plans the column blocks, initialises the seed and shift states
+// on the device and runs the per-iteration kernel sequence of kernels.hpp until
+// every (shift, column) pair has frozen, polling one flag array per
+// `poll_every` iterations; the polled iterations can be replayed as one
+// captured hipGraph.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "scocg.h"
+
+using namespace scocg;
+
+namespace {
+
+thread_local std::string g_err;
+
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+void hip_check(hipError_t e, const char* what, int line) {
+  if (e == hipSuccess) return;
+  const int code = (e == hipErrorOutOfMemory) ? SCOCG_ENOMEM : SCOCG_EHIP;
+  throw Error(code, std::string(what) + " failed (line " + std::to_string(line) +
+                        "): " + hipGetErrorString(e));
+}
+#define HIPCHK(x) hip_check((x), #x, __LINE__)
+#define KCHK() hip_check(hipGetLastError(), "kernel launch", __LINE__)
+
+void require(bool ok, const std::string& msg) {
+  if (!ok) throw Error(SCOCG_EINVAL, msg);
+}
+
+// Owning device allocation.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  void alloc(size_t n) {
+    release();
+    if (n == 0) return;
+    HIPCHK(hipMalloc(&p, n));
+    bytes = n;
+  }
+  template <typename U> U* as() const { return static_cast<U*>(p); }
+};
+
+template <typename U>
+void upload(DevBuf& b, const std::vector<U>& v, hipStream_t s) {
+  b.alloc(v.size() * sizeof(U));
+  if (!v.empty()) {
+    HIPCHK(hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(U), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+  }
+}
+
+unsigned nblocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------------------
+struct scocg_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;  // created here because the caller passed NULL
+  int precision = SCOCG_FP64;
+  int nx = 0, ny = 0, nz = 0, nxy = 0, nf = 4, n_proj = 0;
+  int64_t N = 0;
+  int n_atoms = 0;
+  std::vector<double> coef;  // [3][nf+1]
+  // operator arrays on the device (T = double or float by precision)
+  DevBuf vloc, aptr, aidx, aval, aD, prow, patom, pval;
+  // last solve
+  struct Solve {
+    bool ok = false;
+    int B = 0, nb = 0, K = 0, R = 0, nS = 0, nwg = 0, zc = 0, gx = 0, gy = 0;
+    bool full = false;
+    DevBuf r0, r1, z, cols, sh, coef, list, cnt, k5cnt, blk_active, blk_iter, rhs, srow, x, p,
+        dc, part0, part1;
+    int32_t* h_flags = nullptr;
+    ~Solve() {
+      if (h_flags) (void)hipHostFree(h_flags);
+    }
+  };
+  std::unique_ptr<Solve> last;
+};
+
+namespace {
+
+template <typename T>
+Coefs<T> make_coefs(const scocg_ctx& h) {
+  Coefs<T> co{};
+  const int nf = h.nf;
+  for (int k = 0; k <= nf; ++k) {
+    co.cx[k] = (T)h.coef[0 * (nf + 1) + k];
+    co.cy[k] = (T)h.coef[1 * (nf + 1) + k];
+    co.cz[k] = (T)h.coef[2 * (nf + 1) + k];
+  }
+  co.c0 = (T)(h.coef[0] + h.coef[nf + 1] + h.coef[2 * (nf + 1)]);
+  return co;
+}
+
+template <typename T>
+void upload_operator(scocg_ctx& h, const double* vloc, const int64_t* atom_ptr,
+                     const int64_t* atom_idx, const double* atom_P, const double* atom_D) {
+  hipStream_t s = h.stream;
+  std::vector<T> v(h.N);
+  for (int64_t i = 0; i < h.N; ++i) v[i] = (T)vloc[i];
+  upload(h.vloc, v, s);
+  if (h.n_atoms == 0) return;
+  const int np = h.n_proj;
+  const int64_t E = atom_ptr[h.n_atoms];
+  std::vector<int32_t> ap(h.n_atoms + 1), ai(E);
+  std::vector<T> av(E * 4, (T)0), ad(h.n_atoms * 4, (T)0);
+  for (int a = 0; a <= h.n_atoms; ++a) ap[a] = (int32_t)atom_ptr[a];
+  for (int64_t e = 0; e < E; ++e) {
+    ai[e] = (int32_t)atom_idx[e];
+    for (int l = 0; l < np; ++l) av[e * 4 + l] = (T)atom_P[e * np + l];
+  }
+  for (int a = 0; a < h.n_atoms; ++a)
+    for (int l = 0; l < np; ++l) ad[a * 4 + l] = (T)atom_D[a * np + l];
+  // transpose to point-major CSR: entries of one point in atom order
+  std::vector<int32_t> pr(h.N + 1, 0), pa(E);
+  std::vector<T> pv(E * 4);
+  for (int64_t e = 0; e < E; ++e) pr[ai[e] + 1]++;
+  for (int64_t i = 0; i < h.N; ++i) pr[i + 1] += pr[i];
+  std::vector<int32_t> fill(pr.begin(), pr.end() - 1);
+  for (int a = 0; a < h.n_atoms; ++a)
+    for (int64_t e = ap[a]; e < ap[a + 1]; ++e) {
+      const int32_t slot = fill[ai[e]]++;
+      pa[slot] = a;
+      for (int l = 0; l < 4; ++l) pv[(int64_t)slot * 4 + l] = av[e * 4 + l];
+    }
+  upload(h.aptr, ap, s);
+  upload(h.aidx, ai, s);
+  upload(h.aval, av, s);
+  upload(h.aD, ad, s);
+  upload(h.prow, pr, s);
+  upload(h.patom, pa, s);
+  upload(h.pval, pv, s);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Solver for one precision: T = vector/stencil arithmetic type, B = columns per block.
+template <typename T, int B>
+struct Solver {
+  using cT = typename cplx_of<T>::type;
+  scocg_ctx& h;
+  scocg_ctx::Solve& S;
+  explicit Solver(scocg_ctx& hh, scocg_ctx::Solve& ss) : h(hh), S(ss) {}
+
+  template <int MODE>
+  void launch_stencil(const cT* r, cT* io, const ColState* cols, const int32_t* blk_active,
+                      int nb, int gx, int gy, int zc, double2* part0, double* part1,
+                      const cT* dc) {
+    StencilArgs<T> a{};
+    a.r = r;
+    a.io = io;
+    a.vloc = h.vloc.as<T>();
+    a.co = make_coefs<T>(h);
+    a.nx = h.nx; a.ny = h.ny; a.nz = h.nz; a.nxy = h.nxy;
+    a.zc = zc;
+    a.prow = h.n_atoms ? h.prow.as<int32_t>() : nullptr;
+    a.patom = h.patom.as<int32_t>();
+    a.pval = h.pval.as<T>();
+    a.dc = dc;
+    a.n_atoms = h.n_atoms;
+    a.cols = cols;
+    a.blk_active = blk_active;
+    a.part0 = part0;
+    a.part1 = part1;
+    dim3 grid(gx, gy, nb);
+    switch (h.nf) {
+      case 1: hipLaunchKernelGGL((k_stencil<T, 1, B, MODE>), grid, dim3(WG), 0, h.stream, a); break;
+      case 2: hipLaunchKernelGGL((k_stencil<T, 2, B, MODE>), grid, dim3(WG), 0, h.stream, a); break;
+      case 3: hipLaunchKernelGGL((k_stencil<T, 3, B, MODE>), grid, dim3(WG), 0, h.stream, a); break;
+      default: hipLaunchKernelGGL((k_stencil<T, 4, B, MODE>), grid, dim3(WG), 0, h.stream, a); break;
+    }
+    KCHK();
+  }
+
+  void launch_proj(const cT* r, int nb, cT* dc, const int32_t* blk_active) {
+    if (!h.n_atoms) return;
+    hipLaunchKernelGGL((k_proj<T, B>), dim3(h.n_atoms, nb), dim3(WG), 0, h.stream, r, h.N,
+                       h.aptr.as<int32_t>(), h.aidx.as<int32_t>(), h.aval.as<T>(),
+                       h.aD.as<T>(), h.n_proj, h.n_atoms, dc, blk_active);
+    KCHK();
+  }
+
+  // grid of the stencil pass: PTS x-y points per workgroup, zc planes per workgroup
+  void plan_grid(int nb, int& gx, int& gy, int& zc) const {
+    constexpr int PTS = WG / B;
+    gx = (int)nblocks(h.nxy, PTS);
+    zc = 32;
+    while (zc > 4 && (int64_t)gx * nblocks(h.nz, zc) * nb < 4096) zc /= 2;
+    gy = (int)nblocks(h.nz, zc);
+  }
+
+  // ev: null, or 2*SCOCG_K_FAMILIES events recorded around the launches of this iteration
+  void mark(hipEvent_t* ev, int fam, int end) {
+    if (ev) HIPCHK(hipEventRecord(ev[2 * fam + end], h.stream));
+  }
+
+  void one_iteration(int cur, int par, const scocg_solve_opts& o, hipEvent_t* ev) {
+    cT* rc = (cur ? S.r1 : S.r0).template as<cT>();
+    cT* rn = (cur ? S.r0 : S.r1).template as<cT>();
+    const int32_t* act = S.blk_active.as<int32_t>();
+    mark(ev, SCOCG_K_PROJ, 0);
+    launch_proj(rc, S.nb, S.dc.as<cT>(), act);
+    mark(ev, SCOCG_K_PROJ, 1);
+    mark(ev, SCOCG_K_MU, 0);
+    launch_stencil<MODE_MU>(rc, nullptr, S.cols.as<ColState>(), act, S.nb, S.gx, S.gy, S.zc,
+                            S.part0.as<double2>(), nullptr, S.dc.as<cT>());
+    mark(ev, SCOCG_K_MU, 1);
+    mark(ev, SCOCG_K_ALPHA, 0);
+    hipLaunchKernelGGL((k_alpha<B>), dim3(S.nb), dim3(WG), 0, h.stream, S.part0.as<double2>(),
+                       S.nwg, S.cols.as<ColState>(), cur, act);
+    KCHK();
+    mark(ev, SCOCG_K_ALPHA, 1);
+    mark(ev, SCOCG_K_UPDATE, 0);
+    launch_stencil<MODE_UPDATE>(rc, rn, S.cols.as<ColState>(), act, S.nb, S.gx, S.gy, S.zc,
+                                S.part0.as<double2>(), S.part1.as<double>(), S.dc.as<cT>());
+    mark(ev, SCOCG_K_UPDATE, 1);
+    ControlArgs ca{};
+    ca.part_rho = S.part0.as<double2>();
+    ca.part_nu = S.part1.as<double>();
+    ca.nwg = S.nwg;
+    ca.cols = S.cols.as<ColState>();
+    ca.sh = S.sh.as<ShiftState>();
+    ca.coef = S.coef.as<ShiftCoef>();
+    ca.z = S.z.as<double2>();
+    ca.K = S.K;
+    ca.list = S.list.as<int32_t>();
+    ca.cnt = S.cnt.as<int32_t>();
+    ca.k5cnt = S.k5cnt.as<int32_t>();
+    ca.blk_active = S.blk_active.as<int32_t>();
+    ca.blk_iter = S.blk_iter.as<int32_t>();
+    ca.par = par;
+    ca.buf_new = cur ^ 1;
+    ca.tol = o.tol;
+    ca.max_iter = o.max_iter;
+    ca.seed_switch = o.seed_switch;
+    mark(ev, SCOCG_K_CONTROL, 0);
+    hipLaunchKernelGGL((k_control<B>), dim3(S.nb), dim3(WG), 0, h.stream, ca);
+    KCHK();
+    mark(ev, SCOCG_K_CONTROL, 1);
+    mark(ev, SCOCG_K_SHIFT, 0);
+    constexpr int KCH = 16;
+    const int64_t rows = (int64_t)S.nS * B;
+    dim3 g5(nblocks(rows, WG), nblocks(S.K, KCH), S.nb);
+    hipLaunchKernelGGL((k_shift<T, B, KCH>), g5, dim3(WG), 0, h.stream, rn, h.N,
+                       S.full ? nullptr : S.srow.as<int32_t>(), S.nS,
+                       S.list.as<int32_t>() + (int64_t)par * S.nb * S.K, S.k5cnt.as<int32_t>(),
+                       S.K, S.coef.as<ShiftCoef>(), S.x.as<double2>(), S.p.as<cT>());
+    KCHK();
+    mark(ev, SCOCG_K_SHIFT, 1);
+  }
+
+  int run(int K, const double* z, int R, const int64_t* rhs_idx, int nS_in, const int64_t* s_idx,
+          const scocg_solve_opts& o, scocg_report* rep) {
+    require((R + B - 1) / B <= 65536, "too many column blocks");
+    S.B = B;
+    S.K = K;
+    S.R = R;
+    S.nb = (R + B - 1) / B;
+    S.full = o.full != 0;
+    S.nS = S.full ? (int)h.N : (s_idx ? nS_in : R);
+    const int nb = S.nb;
+    hipStream_t st = h.stream;
+    // inputs
+    std::vector<double2> zh(K);
+    for (int k = 0; k < K; ++k) zh[k] = mk(z[2 * k], z[2 * k + 1]);
+    std::vector<int32_t> rh(R);
+    for (int j = 0; j < R; ++j) rh[j] = (int32_t)rhs_idx[j];
+    upload(S.rhs, rh, st);
+    if (!S.full) {
+      std::vector<int32_t> sr(S.nS);
+      for (int i = 0; i < S.nS; ++i) sr[i] = (int32_t)(s_idx ? s_idx[i] : rhs_idx[i]);
+      upload(S.srow, sr, st);
+    }
+    DevBuf zk;
+    upload(zk, zh, st);
+    // state
+    plan_grid(nb, S.gx, S.gy, S.zc);
+    S.nwg = S.gx * S.gy;
+    const size_t vec = (size_t)nb * h.N * B * sizeof(cT);
+    S.r0.alloc(vec);
+    S.r1.alloc(vec);
+    const size_t nkb = (size_t)nb * K * B;
+    S.z.alloc(nkb * sizeof(double2));
+    S.sh.alloc(nkb * sizeof(ShiftState));
+    S.coef.alloc(nkb * sizeof(ShiftCoef));
+    S.cols.alloc((size_t)nb * B * sizeof(ColState));
+    S.list.alloc((size_t)2 * nb * K * sizeof(int32_t));
+    S.cnt.alloc((size_t)2 * nb * sizeof(int32_t));
+    S.k5cnt.alloc((size_t)nb * sizeof(int32_t));
+    S.blk_active.alloc((size_t)nb * sizeof(int32_t));
+    S.blk_iter.alloc((size_t)nb * sizeof(int32_t));
+    const size_t xp = nkb * (size_t)S.nS;
+    S.x.alloc(xp * sizeof(double2));
+    S.p.alloc(xp * sizeof(cT));
+    S.dc.alloc((size_t)std::max(h.n_atoms, 1) * nb * 4 * B * sizeof(cT));
+    S.part0.alloc((size_t)nb * S.nwg * B * sizeof(double2));
+    S.part1.alloc((size_t)nb * S.nwg * B * sizeof(double));
+    if (!S.h_flags) HIPCHK(hipHostMalloc((void**)&S.h_flags, sizeof(int32_t) * 65536));
+
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    HIPCHK(hipEventRecord(e0, st));
+    const int seed0 = o.init_seed < 0 ? K / 2 : o.init_seed;
+    hipLaunchKernelGGL((k_init_r<T, B>), dim3(nblocks((int64_t)nb * h.N * B, WG)), dim3(WG), 0,
+                       st, S.r0.as<cT>(), S.r1.as<cT>(), h.N, S.rhs.as<int32_t>(), R, nb);
+    KCHK();
+    hipLaunchKernelGGL((k_init_xp<T, B>), dim3(nblocks((int64_t)xp, WG)), dim3(WG), 0, st,
+                       S.x.as<double2>(), S.p.as<cT>(), S.full ? nullptr : S.srow.as<int32_t>(),
+                       S.nS, K, nb, S.rhs.as<int32_t>(), R);
+    KCHK();
+    hipLaunchKernelGGL((k_init_state<B>), dim3(nblocks((int64_t)nkb, WG)), dim3(WG), 0, st,
+                       S.cols.as<ColState>(), S.sh.as<ShiftState>(), S.coef.as<ShiftCoef>(),
+                       S.z.as<double2>(), zk.as<double2>(), K, nb, R, seed0, S.list.as<int32_t>(),
+                       S.cnt.as<int32_t>(), S.k5cnt.as<int32_t>(), S.blk_active.as<int32_t>(),
+                       S.blk_iter.as<int32_t>());
+    KCHK();
+
+    int poll = o.poll_every > 0 ? o.poll_every : 16;
+    if (poll & 1) ++poll;  // even: the buffer and list parities return to 0 after each poll
+    int64_t it = 0;
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    // timing: one event pair per kernel family per iteration of a poll chunk
+    std::vector<hipEvent_t> evs;
+    if (o.timing) {
+      evs.resize((size_t)poll * 2 * SCOCG_K_FAMILIES);
+      for (auto& e : evs) HIPCHK(hipEventCreate(&e));
+    }
+    double kms[SCOCG_K_FAMILIES] = {0};
+    int64_t kcount[SCOCG_K_FAMILIES] = {0};
+    auto ev_of = [&](int s2) { return o.timing ? &evs[(size_t)s2 * 2 * SCOCG_K_FAMILIES] : nullptr; };
+    // events cannot be read back from captured graph nodes: timing runs use direct launches
+    const bool use_graph = o.use_graph && !o.timing;
+    while (true) {
+      if (use_graph) {
+        if (!gexec) {
+          HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+          for (int s2 = 0; s2 < poll; ++s2) one_iteration(s2 & 1, s2 & 1, o, ev_of(s2));
+          HIPCHK(hipStreamEndCapture(st, &graph));
+          HIPCHK(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+        }
+        HIPCHK(hipGraphLaunch(gexec, st));
+      } else {
+        for (int s2 = 0; s2 < poll; ++s2) one_iteration(s2 & 1, s2 & 1, o, ev_of(s2));
+      }
+      it += poll;
+      HIPCHK(hipMemcpyAsync(S.h_flags, S.blk_active.p, nb * sizeof(int32_t),
+                            hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      if (o.timing) {
+        for (int s2 = 0; s2 < poll; ++s2)
+          for (int f = 0; f < SCOCG_K_FAMILIES; ++f) {
+            if (f == SCOCG_K_PROJ && !h.n_atoms) continue;
+            float t = 0.f;
+            hipEvent_t* e = ev_of(s2);
+            HIPCHK(hipEventElapsedTime(&t, e[2 * f], e[2 * f + 1]));
+            kms[f] += t;
+            kcount[f] += 1;
+          }
+      }
+      int any = 0;
+      for (int b = 0; b < nb; ++b) any |= S.h_flags[b];
+      if (!any || it >= o.max_iter + poll) break;
+    }
+    for (auto& e : evs) (void)hipEventDestroy(e);
+    HIPCHK(hipEventRecord(e1, st));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+
+    // report
+    std::vector<ShiftState> shh(nkb);
+    std::vector<ColState> ch((size_t)nb * B);
+    std::vector<int32_t> bit(nb);
+    HIPCHK(hipMemcpy(bit.data(), S.blk_iter.p, nb * sizeof(int32_t), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(shh.data(), S.sh.p, nkb * sizeof(ShiftState), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(ch.data(), S.cols.p, ch.size() * sizeof(ColState), hipMemcpyDeviceToHost));
+    int rc = SCOCG_OK;
+    int64_t seed_iters = 0, nsw = 0;
+    for (int j = 0; j < R; ++j) {
+      seed_iters = std::max<int64_t>(seed_iters, ch[j].iters);
+      nsw += ch[j].nswitch;
+    }
+    for (int k = 0; k < K; ++k)
+      for (int j = 0; j < R; ++j) {
+        const ShiftState& ss = shh[((size_t)(j / B) * K + k) * B + (j % B)];
+        int stt = ss.status;
+        if (ss.active) stt = ST_MAXITER;
+        if (stt == ST_MAXITER && rc == SCOCG_OK) rc = SCOCG_NOT_ALL_CONVERGED;
+        if (stt == ST_BREAKDOWN) rc = SCOCG_BREAKDOWN;
+        const size_t o2 = (size_t)k * R + j;
+        if (rep) {
+          if (rep->iters) rep->iters[o2] = ss.iters;
+          if (rep->est_resid) rep->est_resid[o2] = ss.est;
+          if (rep->true_resid) rep->true_resid[o2] = NAN;
+          if (rep->status) rep->status[o2] = stt;
+        }
+      }
+    if (rep) {
+      rep->seed_iters = seed_iters;
+      rep->n_switches = nsw;
+      rep->refined = 0;
+      rep->solve_ms = ms;
+      rep->block_iters = 0;
+      for (int b = 0; b < nb; ++b) rep->block_iters += bit[b];
+      rep->block_width = B;
+      rep->n_blocks = nb;
+      for (int f = 0; f < SCOCG_K_FAMILIES; ++f) {
+        rep->kernel_ms[f] = kms[f];
+        rep->kernel_launches[f] = kcount[f];
+      }
+    }
+    // release the Krylov workspace; x stays for scocg_green_columns
+    S.r0.release();
+    S.r1.release();
+    S.part0.release();
+    S.part1.release();
+    S.dc.release();
+    S.ok = true;
+    return rc;
+  }
+};
+
+template <typename T, int B>
+void apply_h_impl(scocg_ctx& h, const void* x, void* y) {
+  using cT = typename cplx_of<T>::type;
+  scocg_ctx::Solve tmp;
+  Solver<T, B> sv(h, tmp);
+  DevBuf blk, out, dc;
+  blk.alloc((size_t)h.N * B * sizeof(cT));
+  out.alloc((size_t)h.N * B * sizeof(cT));
+  dc.alloc((size_t)std::max(h.n_atoms, 1) * 4 * B * sizeof(cT));
+  hipLaunchKernelGGL((k_scatter_col0<T, B>), dim3(nblocks(h.N * B, WG)), dim3(WG), 0, h.stream,
+                     static_cast<const double2*>(x), blk.as<cT>(), h.N);
+  KCHK();
+  sv.launch_proj(blk.as<cT>(), 1, dc.as<cT>(), nullptr);
+  int gx, gy, zc;
+  sv.plan_grid(1, gx, gy, zc);
+  sv.template launch_stencil<MODE_APPLY>(blk.as<cT>(), out.as<cT>(), nullptr, nullptr, 1, gx, gy,
+                                         zc, nullptr, nullptr, dc.as<cT>());
+  hipLaunchKernelGGL((k_gather_col0<T, B>), dim3(nblocks(h.N, WG)), dim3(WG), 0, h.stream,
+                     out.as<cT>(), static_cast<double2*>(y), h.N);
+  KCHK();
+  HIPCHK(hipStreamSynchronize(h.stream));
+}
+
+bool all_finite(const double* p, int64_t n) {
+  for (int64_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+template <typename F>
+int guarded(F&& f) {
+  try {
+    g_err.clear();
+    return f();
+  } catch (const Error& e) {
+    g_err = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_err = "host allocation failed";
+    return SCOCG_ENOMEM;
+  } catch (const std::exception& e) {
+    g_err = e.what();
+    return SCOCG_EHIP;
+  }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------------------ C ABI
+extern "C" {
+
+int scocg_create(const scocg_grid* g, const double* coef, const double* vloc, int32_t n_atoms,
+                 const int64_t* atom_ptr, const int64_t* atom_idx, const double* atom_P,
+                 const double* atom_D, int32_t precision, void* hip_stream, scocg_handle* out) {
+  return guarded([&]() -> int {
+    require(out != nullptr, "out is NULL");
+    *out = nullptr;
+    require(g != nullptr && coef != nullptr && vloc != nullptr, "grid, coef or vloc is NULL");
+    require(g->nf >= 1 && g->nf <= 4, "nf must be 1..4");
+    require(g->nx >= g->nf && g->ny >= g->nf && g->nz >= 1, "need nx, ny >= nf and nz >= 1");
+    require(g->nx * g->ny <= (1 << 30) && g->nx * g->ny * g->nz <= ((int64_t)1 << 31) / 32,
+            "grid too large for 32-bit point indices");
+    require(g->n_proj >= 0 && g->n_proj <= 4, "n_proj must be 0..4");
+    require(precision == SCOCG_FP64 || precision == SCOCG_MIXED, "unknown precision");
+    require(n_atoms >= 0, "n_atoms < 0");
+    auto h = std::make_unique<scocg_ctx>();
+    h->nx = (int)g->nx;
+    h->ny = (int)g->ny;
+    h->nz = (int)g->nz;
+    h->nxy = h->nx * h->ny;
+    h->N = (int64_t)h->nxy * h->nz;
+    h->nf = g->nf;
+    h->n_proj = g->n_proj;
+    h->precision = precision;
+    HIPCHK(hipGetDevice(&h->device));
+    h->stream = static_cast<hipStream_t>(hip_stream);
+    if (!h->stream) {  // a private stream, so that solves can be graph-captured
+      HIPCHK(hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking));
+      h->own_stream = true;
+    }
+    require(all_finite(coef, 3 * (g->nf + 1)), "non-finite stencil coefficient");
+    require(all_finite(vloc, h->N), "non-finite local potential");
+    h->coef.assign(coef, coef + 3 * (g->nf + 1));
+    if (n_atoms > 0) {
+      require(g->n_proj >= 1, "atoms given but n_proj = 0");
+      require(atom_ptr && atom_idx && atom_P && atom_D, "atom arrays are NULL");
+      require(atom_ptr[0] == 0, "atom_ptr[0] != 0");
+      for (int a = 0; a < n_atoms; ++a) {
+        require(atom_ptr[a + 1] >= atom_ptr[a], "atom_ptr decreasing");
+        std::vector<int64_t> idx(atom_idx + atom_ptr[a], atom_idx + atom_ptr[a + 1]);
+        for (int64_t v : idx) require(v >= 0 && v < h->N, "atom_idx out of range");
+        std::sort(idx.begin(), idx.end());
+        require(std::adjacent_find(idx.begin(), idx.end()) == idx.end(),
+                "grid index repeated within one atom");
+      }
+      require(atom_ptr[n_atoms] < ((int64_t)1 << 31), "too many projector entries");
+      require(all_finite(atom_P, atom_ptr[n_atoms] * g->n_proj), "non-finite projector value");
+      require(all_finite(atom_D, (int64_t)n_atoms * g->n_proj), "non-finite projector energy");
+    }
+    h->n_atoms = n_atoms;
+    if (precision == SCOCG_FP64)
+      upload_operator<double>(*h, vloc, atom_ptr, atom_idx, atom_P, atom_D);
+    else
+      upload_operator<float>(*h, vloc, atom_ptr, atom_idx, atom_P, atom_D);
+    *out = h.release();
+    return SCOCG_OK;
+  });
+}
+
+int scocg_solve(scocg_handle h, int32_t K, const double* z, int32_t R, const int64_t* rhs_idx,
+                int32_t nS, const int64_t* s_idx, const scocg_solve_opts* opts,
+                scocg_report* rep) {
+  return guarded([&]() -> int {
+    require(h != nullptr, "handle is NULL");
+    require(K >= 1 && z != nullptr, "need K >= 1 energies");
+    require(R >= 1 && rhs_idx != nullptr, "need R >= 1 right-hand sides");
+    for (int k = 0; k < K; ++k) {
+      require(std::isfinite(z[2 * k]) && std::isfinite(z[2 * k + 1]), "non-finite energy");
+      require(z[2 * k + 1] > 0.0, "every energy needs Im z > 0");
+    }
+    for (int j = 0; j < R; ++j) require(rhs_idx[j] >= 0 && rhs_idx[j] < h->N, "rhs_idx out of range");
+    scocg_solve_opts o{};
+    if (opts) o = *opts;
+    if (!(o.tol > 0.0)) o.tol = 1e-10;
+    require(std::isfinite(o.tol), "non-finite tol");
+    if (o.max_iter <= 0) o.max_iter = 100000;
+    require(o.init_seed >= -1 && o.init_seed < K, "init_seed out of range");
+    if (!o.full) {
+      if (s_idx) {
+        require(nS >= 1, "nS must be >= 1 with s_idx");
+        for (int i = 0; i < nS; ++i) require(s_idx[i] >= 0 && s_idx[i] < h->N, "s_idx out of range");
+      } else {
+        require(nS == 0, "nS > 0 needs s_idx");
+      }
+    }
+    HIPCHK(hipSetDevice(h->device));
+    h->last.reset(new scocg_ctx::Solve());
+    if (h->precision == SCOCG_FP64) {
+      Solver<double, 8> sv(*h, *h->last);
+      return sv.run(K, z, R, rhs_idx, nS, s_idx, o, rep);
+    }
+    Solver<float, 16> sv(*h, *h->last);
+    return sv.run(K, z, R, rhs_idx, nS, s_idx, o, rep);
+  });
+}
+
+int scocg_green_columns(scocg_handle h, void* dst, int32_t dtype, int32_t dst_is_device) {
+  return guarded([&]() -> int {
+    require(h != nullptr && dst != nullptr, "handle or dst is NULL");
+    require(dtype == SCOCG_C128 || dtype == SCOCG_C64, "unknown dtype");
+    if (!h->last || !h->last->ok) throw Error(SCOCG_ENOSOLVE, "no successful solve to copy");
+    HIPCHK(hipSetDevice(h->device));
+    auto& S = *h->last;
+    const int64_t tot = (int64_t)S.K * S.R * S.nS;
+    const size_t esz = dtype == SCOCG_C128 ? 16 : 8;
+    DevBuf tmp;
+    void* d = dst;
+    if (!dst_is_device) {
+      tmp.alloc(tot * esz);
+      d = tmp.p;
+    }
+    const unsigned nbk = nblocks(tot, WG);
+    if (S.B == 8) {
+      if (dtype == SCOCG_C128)
+        hipLaunchKernelGGL((k_gather_out<8, double2>), dim3(nbk), dim3(WG), 0, h->stream,
+                           S.x.as<double2>(), static_cast<double2*>(d), S.K, S.R, S.nS);
+      else
+        hipLaunchKernelGGL((k_gather_out<8, float2>), dim3(nbk), dim3(WG), 0, h->stream,
+                           S.x.as<double2>(), static_cast<float2*>(d), S.K, S.R, S.nS);
+    } else {
+      if (dtype == SCOCG_C128)
+        hipLaunchKernelGGL((k_gather_out<16, double2>), dim3(nbk), dim3(WG), 0, h->stream,
+                           S.x.as<double2>(), static_cast<double2*>(d), S.K, S.R, S.nS);
+      else
+        hipLaunchKernelGGL((k_gather_out<16, float2>), dim3(nbk), dim3(WG), 0, h->stream,
+                           S.x.as<double2>(), static_cast<float2*>(d), S.K, S.R, S.nS);
+    }
+    KCHK();
+    if (!dst_is_device)
+      HIPCHK(hipMemcpyAsync(dst, d, tot * esz, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return SCOCG_OK;
+  });
+}
+
+int scocg_apply_h(scocg_handle h, const void* x_dev, void* y_dev) {
+  return guarded([&]() -> int {
+    require(h != nullptr && x_dev != nullptr && y_dev != nullptr, "NULL argument");
+    HIPCHK(hipSetDevice(h->device));
+    if (h->precision == SCOCG_FP64)
+      apply_h_impl<double, 8>(*h, x_dev, y_dev);
+    else
+      apply_h_impl<float, 16>(*h, x_dev, y_dev);
+    return SCOCG_OK;
+  });
+}
+
+void scocg_destroy(scocg_handle h) {
+  if (!h) return;
+  (void)hipSetDevice(h->device);
+  (void)hipStreamSynchronize(h->stream);
+  hipStream_t s = h->own_stream ? h->stream : nullptr;
+  delete h;
+  if (s) (void)hipStreamDestroy(s);
+}
+
+const char* scocg_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,210 @@
+"""Python binding of the scocg C ABI (include/scocg.h): argument marshalling only.
+
+Every step of the solve runs in the HIP library libscocg.so; this module
+converts numpy arrays to pointers and back.  Device buffers may be passed as
+torch tensors (their data_ptr() is used); PyTorch is only a source of device
+memory and streams here.  If the library has not been built, loading fails
+with an error -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libscocg.so")
+
+OK, EINVAL, ENOMEM, EHIP, ENOSOLVE = 0, -1, -2, -3, -4
+NOT_ALL_CONVERGED, BREAKDOWN = 1, 2
+FP64, MIXED = 0, 1
+PAIR_CONVERGED, PAIR_MAXITER, PAIR_BREAKDOWN = 0, 1, 2
+C128, C64 = 0, 1
+
+EXPORTS = ("scocg_create", "scocg_solve", "scocg_green_columns", "scocg_apply_h",
+           "scocg_destroy", "scocg_last_error")
+
+
+class Grid(C.Structure):
+    _fields_ = [("nx", C.c_int64), ("ny", C.c_int64), ("nz", C.c_int64),
+                ("nf", C.c_int32), ("n_proj", C.c_int32)]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int64), ("init_seed", C.c_int32),
+                ("seed_switch", C.c_int32), ("full", C.c_int32), ("refine", C.c_int32),
+                ("poll_every", C.c_int32), ("use_graph", C.c_int32), ("timing", C.c_int32)]
+
+
+class Report(C.Structure):
+    _fields_ = [("iters", C.c_void_p), ("est_resid", C.c_void_p), ("true_resid", C.c_void_p),
+                ("status", C.c_void_p), ("seed_iters", C.c_int64), ("n_switches", C.c_int64),
+                ("refined", C.c_int64), ("solve_ms", C.c_double), ("block_iters", C.c_int64),
+                ("block_width", C.c_int32), ("n_blocks", C.c_int32),
+                ("kernel_ms", C.c_double * 6), ("kernel_launches", C.c_int64 * 6)]
+
+KERNEL_FAMILIES = ("proj", "mu", "alpha", "update", "control", "shift")
+
+
+class ScocgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"scocg error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libscocg.so (built by paper_1502_00081_amd.build); raises if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build the HIP library first "
+                           "(python -m paper_1502_00081_amd.build)")
+    lib = C.CDLL(path)
+    P = C.c_void_p
+    lib.scocg_create.argtypes = [C.POINTER(Grid), P, P, C.c_int32, P, P, P, P, C.c_int32, P,
+                                 C.POINTER(P)]
+    lib.scocg_create.restype = C.c_int
+    lib.scocg_solve.argtypes = [P, C.c_int32, P, C.c_int32, P, C.c_int32, P,
+                                C.POINTER(SolveOpts), C.POINTER(Report)]
+    lib.scocg_solve.restype = C.c_int
+    lib.scocg_green_columns.argtypes = [P, P, C.c_int32, C.c_int32]
+    lib.scocg_green_columns.restype = C.c_int
+    lib.scocg_apply_h.argtypes = [P, P, P]
+    lib.scocg_apply_h.restype = C.c_int
+    lib.scocg_destroy.argtypes = [P]
+    lib.scocg_destroy.restype = None
+    lib.scocg_last_error.argtypes = []
+    lib.scocg_last_error.restype = C.c_char_p
+    _lib = lib
+    return lib
+
+
+def last_error() -> str:
+    return load().scocg_last_error().decode()
+
+
+def _check(rc):
+    if rc < 0:
+        raise ScocgError(rc, last_error())
+    return rc
+
+
+def _c(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        return None
+    return int(getattr(stream, "cuda_stream", stream))
+
+
+def _dev_ptr(t):
+    return int(t.data_ptr()) if hasattr(t, "data_ptr") else int(t)
+
+
+class Handle:
+    """One uploaded Hamiltonian (scocg_create) and its last solve."""
+
+    def __init__(self, ptr, n, keep):
+        self._h = C.c_void_p(ptr)
+        self.n = n
+        self._keep = keep
+        self.last = None
+
+    def solve(self, z, rhs_idx, s_idx=None, tol=1e-10, max_iter=100000, init_seed=-1,
+              seed_switch=True, full=False, refine=0, poll_every=0, use_graph=False, timing=False):
+        """scocg_solve; returns (rc, report dict with [K, R] arrays)."""
+        lib = load()
+        z = _c(z, np.complex128)
+        rhs = _c(rhs_idx, np.int64)
+        K, R = z.size, rhs.size
+        sp = None
+        nS = 0
+        if s_idx is not None:
+            sp = _c(s_idx, np.int64)
+            nS = sp.size
+        o = SolveOpts(float(tol), int(max_iter), int(init_seed), int(bool(seed_switch)),
+                      int(bool(full)), int(refine), int(poll_every), int(bool(use_graph)),
+                      int(bool(timing)))
+        iters = np.zeros((K, R), np.int64)
+        est = np.zeros((K, R))
+        tres = np.zeros((K, R))
+        status = np.zeros((K, R), np.int32)
+        rep = Report()
+        rep.iters, rep.est_resid = iters.ctypes.data, est.ctypes.data
+        rep.true_resid, rep.status = tres.ctypes.data, status.ctypes.data
+        rc = lib.scocg_solve(self._h, K, z.ctypes.data, R, rhs.ctypes.data, nS,
+                             None if sp is None else sp.ctypes.data, C.byref(o), C.byref(rep))
+        _check(rc)
+        nrows = self.n if full else (nS if sp is not None else R)
+        self.last = (K, R, nrows)
+        return rc, dict(iters=iters, est=est, true_resid=tres, status=status,
+                        seed_iters=rep.seed_iters, n_switches=rep.n_switches,
+                        refined=rep.refined, solve_ms=rep.solve_ms, block_iters=rep.block_iters,
+                        block_width=rep.block_width, n_blocks=rep.n_blocks,
+                        kernel_ms=dict(zip(KERNEL_FAMILIES, list(rep.kernel_ms))),
+                        kernel_launches=dict(zip(KERNEL_FAMILIES, list(rep.kernel_launches))))
+
+    def green_columns(self, out=None, dtype=C128):
+        """scocg_green_columns into `out` (torch device tensor or numpy array), or a new
+        numpy array [K, R, nS]."""
+        lib = load()
+        if out is None:
+            K, R, nS = self.last
+            out = np.zeros((K, R, nS), np.complex128 if dtype == C128 else np.complex64)
+        if isinstance(out, np.ndarray):
+            assert out.flags.c_contiguous
+            _check(lib.scocg_green_columns(self._h, out.ctypes.data, dtype, 0))
+        else:
+            _check(lib.scocg_green_columns(self._h, _dev_ptr(out), dtype, 1))
+        return out
+
+    def apply_h(self, x_dev, y_dev):
+        """scocg_apply_h on complex128 device vectors (torch tensors or raw pointers)."""
+        _check(load().scocg_apply_h(self._h, _dev_ptr(x_dev), _dev_ptr(y_dev)))
+
+    def destroy(self):
+        if self._h:
+            load().scocg_destroy(self._h)
+            self._h = C.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def create(nx, ny, nz, nf, coef, vloc, atom_ptr=None, atom_idx=None, atom_P=None, atom_D=None,
+           precision=FP64, stream=None) -> Handle:
+    """scocg_create from numpy arrays (shapes as in include/scocg.h)."""
+    lib = load()
+    coef = _c(coef, np.float64)
+    vloc = _c(vloc, np.float64)
+    n_atoms = 0 if atom_ptr is None else int(np.asarray(atom_ptr).size - 1)
+    keep = [coef, vloc]
+    ptrs = [None, None, None, None]
+    n_proj = 0
+    if n_atoms > 0:
+        ap, ai = _c(atom_ptr, np.int64), _c(atom_idx, np.int64)
+        aP, aD = _c(atom_P, np.float64), _c(atom_D, np.float64)
+        n_proj = aD.shape[1]
+        keep += [ap, ai, aP, aD]
+        ptrs = [a.ctypes.data for a in (ap, ai, aP, aD)]
+    g = Grid(nx, ny, nz, nf, n_proj)
+    out = C.c_void_p()
+    _check(lib.scocg_create(C.byref(g), coef.ctypes.data, vloc.ctypes.data, n_atoms, *ptrs,
+                            int(precision), _stream_ptr(stream), C.byref(out)))
+    return Handle(out.value, nx * ny * nz, keep)
+
+
+def create_from_problem(p, precision=FP64, stream=None) -> Handle:
+    """scocg_create for an object with the fields of workload.Problem."""
+    return create(p.nx, p.ny, p.nz, p.nf, p.coef, p.vloc, p.atom_ptr, p.atom_idx, p.atom_P,
+                  p.atom_D, precision=precision, stream=stream)
