@@ -25,6 +25,10 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBPS = 8000.0
 
 
+def say(msg):
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -40,22 +44,34 @@ def parse():
 
 
 def cpu_baseline(p, n_pairs, tol):
-    """Oracle (plain C, OpenMP over pairs) on a fixed sample of (energy, column) pairs."""
+    """Oracle (plain C, one pair per host thread) on a fixed sample of (energy, column)
+    pairs spread over the energy window."""
+    from concurrent.futures import ThreadPoolExecutor
+
     import oracle
     K, R = p.z.size, p.rhs_idx.size
     rng = np.random.default_rng(2024)
     ks = np.linspace(0, K - 1, n_pairs).round().astype(int)
     js = rng.choice(R, n_pairs, replace=n_pairs > R)
     pairs = list(zip(ks.tolist(), js.tolist()))
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    threads = min(n_pairs, int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
+
+    def one(kj):
+        _, it, st, _ = oracle.cocg_unit_columns(p, p.z, p.rhs_idx, p.rhs_idx, [kj], tol=tol)
+        say(f"cpu baseline pair {kj}: {int(it[0])} iterations")
+        return int(it[0]), int(st[0])
+
     t0 = time.perf_counter()
-    _, it, st, _ = oracle.cocg_unit_columns(p, p.z, p.rhs_idx, p.rhs_idx, pairs, tol=tol)
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        res = list(ex.map(one, pairs))
     dt = time.perf_counter() - t0
-    conv = int((st == oracle.CONVERGED).sum())
+    conv = sum(1 for _, s in res if s == oracle.CONVERGED)
+    mean_it = float(np.mean([i for i, _ in res]))
     return {"value": conv / dt, "unit": "solves/s", "cores": threads, "kind": "oracle",
-            "sample": f"{n_pairs} (energy, column) pairs of the same workload, energies spread "
-                      f"over the window, columns seeded; conventional FP64 COCG per pair to "
-                      f"{tol:g}; {dt:.1f} s wall, mean {it.mean():.0f} iterations"}
+            "sample": f"{n_pairs} (energy, column) pairs of the same workload (energies evenly "
+                      f"spread over the window, columns seeded), conventional FP64 COCG per "
+                      f"pair to {tol:g}, one pair per thread; {dt:.1f} s wall, mean "
+                      f"{mean_it:.0f} iterations per pair"}
 
 
 def main():
@@ -75,16 +91,20 @@ def main():
     K, R = p.z.size, p.rhs_idx.size
     out = torch.empty((K, R, R), dtype=torch.complex128, device="cuda")
     kw = dict(tol=a.tol, timing=True)
-    for _ in range(a.warmup):
-        h.solve(p.z, p.rhs_idx, **kw)
+    say(f"workload {p.name}: N={p.n}, K={K}, R={R}, precision {a.precision}")
+    for i in range(a.warmup):
+        rc, rep = h.solve(p.z, p.rhs_idx, **kw)
         h.green_columns(out)
+        say(f"warmup {i}: rc={rc}, {rep['seed_iters']} seed iterations, "
+            f"{rep['solve_ms']:.1f} ms device")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     reps = []
-    for _ in range(a.steps):
+    for i in range(a.steps):
         rc, rep = h.solve(p.z, p.rhs_idx, **kw)
         h.green_columns(out)
         reps.append(rep)
+        say(f"step {i}: rc={rc}, {rep['solve_ms']:.1f} ms device")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     converged = sum(int((r["status"] == scocg.PAIR_CONVERGED).sum()) for r in reps)
@@ -132,6 +152,7 @@ def main():
         line["ms_per_step_graph_replay"] = (time.perf_counter() - tg) * 1e3
     h.destroy()
     if not a.no_cpu_baseline:
+        say(f"cpu baseline: oracle on {a.cpu_pairs} pairs")
         line["cpu_baseline"] = cpu_baseline(p, a.cpu_pairs, a.tol)
     print(json.dumps(line), flush=True)
 
