@@ -106,11 +106,16 @@ typedef struct {
     int32_t timing;      /* 1: bracket every kernel launch with HIP events and report the
                             summed durations per kernel family (scocg_report.kernel_ms);
                             launches are then direct (use_graph is ignored) */
+    int32_t tile;        /* stencil workgroup shape, x-y tile TX x TY and threads per group
+                            (0 -> 1 for SCOCG_FP64, 3 for SCOCG_MIXED). SCOCG_FP64: 1 = 16x8/1024, 2 = 16x4/512,
+                            3 = 8x8/512, 4 = 16x8/512.  SCOCG_MIXED: 1 = 16x8/1024,
+                            2 = 16x4/512, 3 = 8x8/1024, 4 = 8x8/512.  nf < 4 always uses 1 */
+    int32_t zchunk;      /* z planes per stencil workgroup (0 -> chosen from the grid size) */
 } scocg_solve_opts;
 
 /* kernel families of one seed iteration (index into scocg_report.kernel_ms) */
-#define SCOCG_K_PROJ 0     /* projector contraction C_a = D_a P_a^T r_n */
-#define SCOCG_K_MU 1       /* stencil pass: partials of (r_n, A r_n) */
+#define SCOCG_K_PROJ 0     /* (reported as 0: the projector contraction runs inside SCOCG_K_MU) */
+#define SCOCG_K_MU 1       /* stencil pass: partials of (r_n, A r_n) + projector contraction */
 #define SCOCG_K_ALPHA 2    /* seed alpha_n, c_n */
 #define SCOCG_K_UPDATE 3   /* stencil pass: r_{n+1} (three-term recurrence) + dot partials */
 #define SCOCG_K_CONTROL 4  /* beta_n, pi recurrences, convergence, compaction, seed switch */

@@ -7,8 +7,8 @@
 //   shift state         [nb][K][B]        ShiftState (pi_{n-1}, pi_n, status)
 //   column state        [nb*B]            ColState (seed scalars, FP64)
 // Per seed iteration n the host enqueues:
-//   k_proj      C_a = D_a P_a^T r_n for every atom                    (nonlocal part of H)
-//   k_stencil<MU>     partials of mu_n = (r_n, A r_n),  A = z_s - H    (Eq. A5 numerator terms)
+//   k_stencil<MU>     partials of mu_n = (r_n, A r_n),  A = z_s - H    (Eq. A5), plus, in
+//                     extra workgroups, the projector contraction C_a = P_a^T r_n
 //   k_alpha     alpha_n, c_n = beta_{n-1} alpha_n / alpha_{n-1}       (Eq. A5)
 //   k_stencil<UPDATE> r_{n+1} = (1+c_n) r_n - alpha_n A r_n - c_n r_{n-1}  (Eq. A3), in place
 //                     over r_{n-1}; partials of rho_{n+1}, ||r_{n+1}||^2
@@ -66,7 +66,7 @@ struct ColState {
   double2 c;           // beta_{n-1} alpha_n / alpha_{n-1}
   double2 zs;          // current seed energy
   double2 scale[2];    // stored Krylov buffer b holds r / scale[b] (lazy seed-switch rescale)
-  double2 ar, aw, ap;  // r_{n+1} = ar r^st_n + aw (A r^st_n) + ap r^st_{n-1}
+  double2 ar, ah, ap;  // r_{n+1} = ar r^st_n + ah (H r^st_n) + ap r^st_{n-1}
   double bnorm;        // ||b||
   int32_t seed;        // seed shift index
   int32_t done;        // column finished
@@ -105,15 +105,37 @@ template <typename T> struct Coefs {
 // ------------------------------------------------------------------ stencil pass
 enum { MODE_MU = 0, MODE_UPDATE = 1, MODE_APPLY = 2 };
 
+// launch geometry of a stencil pass: tile variant, tiles per plane, z-chunks,
+// partial slots per column block, and the XCD-sliced 1-D grid
+struct StencilGrid {
+  int variant, ntx, nty, zc, nzc, nwg, nper, grid;
+};
+
+template <typename T>
+struct ProjArgs {
+  using cT = typename cplx_of<T>::type;
+  const int32_t* aptr;   // [n_atoms+1] atom-major CSR
+  const int32_t* aidx;   // [E] grid index
+  const T* aval;         // [E][4]
+  const T* aD;           // [n_atoms][4]
+  int n_proj, n_atoms;
+  cT* dc;                // out [nb][n_atoms][4][B]: D_l C_l
+  double2* qa;           // out [nb][n_atoms][B]: sum_l C_l D_l C_l (null: not needed)
+};
+
 template <typename T>
 struct StencilArgs {
   using cT = typename cplx_of<T>::type;
-  const cT* r;           // [nb][N][B] stored r_n
-  cT* io;                // UPDATE: r_{n-1} in, r_{n+1} out; APPLY: H r out
+  const cT* r;           // [nb][nz+2NF][nxy][B] stored r_n, from the first padding plane
+  cT* io;                // same layout; UPDATE: r_{n-1} in, r_{n+1} out; APPLY: H r out
+  int64_t bstride;       // elements per column block ((nz+2NF)*nxy*B)
   const T* vloc;         // [N]
   Coefs<T> co;
   int nx, ny, nz, nxy;
-  int zc;                // planes per workgroup
+  int ntx, nty;          // x-y tiles per plane
+  int zc, nzc;           // planes per workgroup, z-chunks per plane column
+  int nb;                // column blocks in the launch
+  int nper;              // workgroups per XCD slice of the launch (grid = 8 * nper)
   const int32_t* prow;   // [N+1] point -> projector entries (null if no atoms)
   const int32_t* patom;  // [E] atom of each entry
   const T* pval;         // [E][4] projector values
@@ -121,200 +143,491 @@ struct StencilArgs {
   int n_atoms;
   const ColState* cols;  // [nb*B]
   const int32_t* blk_active;  // [nb] (null: all active)
-  double2* part0;        // [nb][n_wg][B] mu or rho partials
-  double* part1;         // [nb][n_wg][B] ||r||^2 partials (UPDATE)
+  double2* part0;        // [nb][nwg][B] mu or rho partials, nwg = nzc*ntx*nty
+  double* part1;         // [nb][nwg][B] ||r||^2 partials (UPDATE)
+  int nproj_wg;          // MU: leading workgroups doing the projector contraction
+  ProjArgs<T> proj;
 };
 
-// One thread owns one (x-y point, column) and marches along z over zc planes
-// with a register queue of the 2*NF+1 z-neighbours; x and y neighbours are
-// read through L1/L2.  Workgroup reductions of the dot partials are in a
-// fixed tree order (bitwise repeatable, no atomics).
-template <typename T, int NF, int B, int MODE>
-__global__ __launch_bounds__(WG) void k_stencil(StencilArgs<T> a) {
-  using cT = typename cplx_of<T>::type;
-  constexpr int PTS = WG / B;
-  const int tid = threadIdx.x;
-  const int c = tid % B;
-  const int pl = tid / B;
-  const int cb = blockIdx.z;
-  if (a.blk_active && !a.blk_active[cb]) return;
-  const int q = blockIdx.x * PTS + pl;
-  const bool valid = q < a.nxy;
-  const int z0 = blockIdx.y * a.zc;
-  const int z1 = min(z0 + a.zc, a.nz);
-  const int64_t N = (int64_t)a.nxy * a.nz;
-  const cT* rb = a.r + (int64_t)cb * N * B + c;
-  const int j = cb * B + c;
+// Component-wise select of two complex values taken by value.  Register arrays
+// of complex values must never meet a select of two aggregate lvalues: the
+// compiler turns that into a select of addresses and moves the arrays to
+// scratch memory.
+template <typename V>
+__device__ __forceinline__ V csel(bool c, V a, V b) {
+  V r;
+  r.x = c ? a.x : b.x;
+  r.y = c ? a.y : b.y;
+  return r;
+}
 
-  int xo_p[NF + 1], xo_m[NF + 1], yo_p[NF + 1], yo_m[NF + 1];
-  {
-    const int qq = valid ? q : 0;
-    const int ix = qq % a.nx, iy = qq / a.nx;
-#pragma unroll
-    for (int k = 1; k <= NF; ++k) {
-      int xp = ix + k; if (xp >= a.nx) xp -= a.nx;
-      int xm = ix - k; if (xm < 0) xm += a.nx;
-      int yp = iy + k; if (yp >= a.ny) yp -= a.ny;
-      int ym = iy - k; if (ym < 0) ym += a.ny;
-      xo_p[k] = xp + iy * a.nx;
-      xo_m[k] = xm + iy * a.nx;
-      yo_p[k] = ix + yp * a.nx;
-      yo_m[k] = ix + ym * a.nx;
-    }
-  }
-  double2 zs = mk(0, 0), ar = mk(0, 0), aw = mk(0, 0), ap = mk(0, 0);
-  if (MODE != MODE_APPLY) {
-    const ColState& cs = a.cols[j];
-    zs = cs.zs;
-    ar = cs.ar; aw = cs.aw; ap = cs.ap;
-  }
-  const T zr = (T)zs.x, zi = (T)zs.y;
+// *p if ok, else zero.  p must be a valid address either way (callers clamp the
+// index into range), so the load is unconditional and only the value is selected.
+template <typename V>
+__device__ __forceinline__ V ld_or_zero(const V* p, bool ok) {
+  V z;
+  z.x = 0;
+  z.y = 0;
+  return csel(ok, *p, z);
+}
 
-  cT Q[2 * NF + 1];
-#pragma unroll
-  for (int d = 0; d < 2 * NF; ++d) {
-    const int iz = z0 - NF + d;
-    Q[d] = (valid && iz >= 0 && iz < a.nz) ? rb[((int64_t)iz * a.nxy + q) * B] : cT{0, 0};
-  }
-  double2 acc0 = mk(0, 0);
-  double acc1 = 0.0;
-  for (int iz = z0; iz < z1; ++iz) {
-    {
-      const int izn = iz + NF;
-      Q[2 * NF] = (valid && izn < a.nz) ? rb[((int64_t)izn * a.nxy + q) * B] : cT{0, 0};
-    }
-    if (valid) {
-      const int64_t pbase = (int64_t)iz * a.nxy;
-      const int64_t p = pbase + q;
-      const cT ctr = Q[NF];
-      const T dg = a.co.c0 + a.vloc[p];
-      T hr = dg * ctr.x, hi = dg * ctr.y;
-#pragma unroll
-      for (int k = 1; k <= NF; ++k) {
-        const cT zp = Q[NF + k], zm = Q[NF - k];
-        const cT xp = rb[(pbase + xo_p[k]) * B], xm = rb[(pbase + xo_m[k]) * B];
-        const cT yp = rb[(pbase + yo_p[k]) * B], ym = rb[(pbase + yo_m[k]) * B];
-        hr += a.co.cz[k] * (zp.x + zm.x) + a.co.cx[k] * (xp.x + xm.x) + a.co.cy[k] * (yp.x + ym.x);
-        hi += a.co.cz[k] * (zp.y + zm.y) + a.co.cx[k] * (xp.y + xm.y) + a.co.cy[k] * (yp.y + ym.y);
-      }
-      if (a.prow) {
-        const int e0 = a.prow[p], e1 = a.prow[p + 1];
-        for (int e = e0; e < e1; ++e) {
-          const cT* dca = a.dc + ((int64_t)cb * a.n_atoms + a.patom[e]) * 4 * B + c;
-          const T* pv = a.pval + (int64_t)e * 4;
-#pragma unroll
-          for (int l = 0; l < 4; ++l) {
-            const cT d = dca[l * B];
-            hr += pv[l] * d.x;
-            hi += pv[l] * d.y;
-          }
-        }
-      }
-      if (MODE == MODE_APPLY) {
-        cT o; o.x = hr; o.y = hi;
-        a.io[(p * B) + (int64_t)cb * N * B + c] = o;
-      } else {
-        // w = (z_s - H) r
-        const T wr = zr * ctr.x - zi * ctr.y - hr;
-        const T wi = zr * ctr.y + zi * ctr.x - hi;
-        if (MODE == MODE_MU) {
-          const double cr = ctr.x, ci = ctr.y;
-          acc0.x += cr * (double)wr - ci * (double)wi;
-          acc0.y += cr * (double)wi + ci * (double)wr;
-        } else {
-          cT* iop = a.io + (int64_t)cb * N * B + p * B + c;
-          const double2 rp = to_d(*iop);
-          const double2 rc = to_d(ctr);
-          const double2 ww = mk(wr, wi);
-          double2 rn = cmul(ar, rc);
-          rn = cadd(rn, cmul(aw, ww));
-          rn = cadd(rn, cmul(ap, rp));
-          const cT rs = from_d<cT>(rn);
-          *iop = rs;
-          const double2 rq = to_d(rs);
-          acc0.x += rq.x * rq.x - rq.y * rq.y;
-          acc0.y += 2.0 * rq.x * rq.y;
-          acc1 += rq.x * rq.x + rq.y * rq.y;
-        }
-      }
-    }
-#pragma unroll
-    for (int d = 0; d < 2 * NF; ++d) Q[d] = Q[d + 1];
-  }
-  if (MODE == MODE_APPLY) return;
-
-  __shared__ double2 s0[WG];
-  __shared__ double s1[WG];
-  s0[tid] = acc0;
-  if (MODE == MODE_UPDATE) s1[tid] = acc1;
-  __syncthreads();
-#pragma unroll
-  for (int s = PTS / 2; s >= 1; s >>= 1) {
-    if (pl < s) {
-      s0[tid] = cadd(s0[tid], s0[tid + s * B]);
-      if (MODE == MODE_UPDATE) s1[tid] += s1[tid + s * B];
-    }
-    __syncthreads();
-  }
-  if (pl == 0) {
-    const int nwg = gridDim.x * gridDim.y;
-    const int wg = blockIdx.x + gridDim.x * blockIdx.y;
-    const int64_t o = ((int64_t)cb * nwg + wg) * B + c;
-    a.part0[o] = s0[tid];
-    if (MODE == MODE_UPDATE) a.part1[o] = s1[tid];
-  }
+__device__ __forceinline__ int wrapi(int v, int n) {
+  v %= n;
+  return v < 0 ? v + n : v;
 }
 
 // ------------------------------------------------------------------ projector contraction
-// dc[cb][a][l][c] = D_a[l] * sum_e P_a[e][l] r[idx_e][c], one workgroup per (atom, block).
-template <typename T, int B>
-__global__ __launch_bounds__(WG) void k_proj(const typename cplx_of<T>::type* __restrict__ r,
-                                              int64_t N, const int32_t* __restrict__ aptr,
-                                              const int32_t* __restrict__ aidx,
-                                              const T* __restrict__ aval, const T* __restrict__ aD,
-                                              int n_proj, int n_atoms,
-                                              typename cplx_of<T>::type* __restrict__ dc,
-                                              const int32_t* __restrict__ blk_active) {
+// For one (atom a, column block): C_l = sum_e P_a[e][l] r[idx_e][c];  dc = D_l C_l;
+// qa = sum_l C_l D_l C_l = r^T P_a D_a P_a^T r (the atom's share of r^T H r).
+// Runs with NT threads; the reduction over entry lanes is a fixed tree in smem.
+// r points at plane 0 of block 0; bstride = elements per column block.
+template <typename T, int B, int NT>
+__device__ __forceinline__ void proj_contract(const typename cplx_of<T>::type* __restrict__ r,
+                                              int64_t bstride, const ProjArgs<T>& pa, int at,
+                                              int cb, char* smem) {
   using cT = typename cplx_of<T>::type;
-  constexpr int PTS = WG / B;
+  constexpr int PL = NT / B;
   const int tid = threadIdx.x, c = tid % B, ln = tid / B;
-  const int at = blockIdx.x, cb = blockIdx.y;
-  if (blk_active && !blk_active[cb]) return;
-  const cT* rb = r + (int64_t)cb * N * B + c;
+  const cT* rb = r + (int64_t)cb * bstride + c;
   T acc[4][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
-  const int e0 = aptr[at], e1 = aptr[at + 1];
-  for (int e = e0 + ln; e < e1; e += PTS) {
-    const cT v = rb[(int64_t)aidx[e] * B];
+  const int e0 = pa.aptr[at], e1 = pa.aptr[at + 1];
+  for (int e = e0 + ln; e < e1; e += PL) {
+    const cT v = rb[(int64_t)pa.aidx[e] * B];
 #pragma unroll
     for (int l = 0; l < 4; ++l) {
-      const T pv = aval[(int64_t)e * 4 + l];
+      const T pv = pa.aval[(int64_t)e * 4 + l];
       acc[l][0] += pv * v.x;
       acc[l][1] += pv * v.y;
     }
   }
-  __shared__ T sh[4][2][WG];
+  T* sh = reinterpret_cast<T*>(smem);  // [4][2][NT]
 #pragma unroll
-  for (int l = 0; l < 4; ++l) { sh[l][0][tid] = acc[l][0]; sh[l][1][tid] = acc[l][1]; }
+  for (int l = 0; l < 4; ++l) {
+    sh[(l * 2 + 0) * NT + tid] = acc[l][0];
+    sh[(l * 2 + 1) * NT + tid] = acc[l][1];
+  }
   __syncthreads();
-  for (int s = PTS / 2; s >= 1; s >>= 1) {
+  for (int s = PL / 2; s >= 1; s >>= 1) {
     if (ln < s) {
 #pragma unroll
-      for (int l = 0; l < 4; ++l) {
-        sh[l][0][tid] += sh[l][0][tid + s * B];
-        sh[l][1][tid] += sh[l][1][tid + s * B];
-      }
+      for (int q = 0; q < 8; ++q) sh[q * NT + tid] += sh[q * NT + tid + s * B];
     }
     __syncthreads();
   }
   if (ln == 0) {
-    cT* o = dc + ((int64_t)cb * n_atoms + at) * 4 * B + c;
+    cT* o = pa.dc + ((int64_t)cb * pa.n_atoms + at) * 4 * B + c;
+    double2 q = mk(0, 0);
 #pragma unroll
     for (int l = 0; l < 4; ++l) {
-      const T d = l < n_proj ? aD[at * 4 + l] : (T)0;
-      cT v; v.x = d * sh[l][0][tid]; v.y = d * sh[l][1][tid];
+      const T d = l < pa.n_proj ? pa.aD[at * 4 + l] : (T)0;
+      const T cr = sh[(l * 2 + 0) * NT + tid], ci = sh[(l * 2 + 1) * NT + tid];
+      cT v;
+      v.x = d * cr;
+      v.y = d * ci;
       o[l * B] = v;
+      // C_l (D_l C_l), unconjugated
+      q.x += (double)cr * v.x - (double)ci * v.y;
+      q.y += (double)cr * v.y + (double)ci * v.x;
+    }
+    if (pa.qa) pa.qa[((int64_t)cb * pa.n_atoms + at) * B + c] = q;
+  }
+}
+
+template <typename T, int B>
+__global__ __launch_bounds__(WG) void k_proj(const typename cplx_of<T>::type* __restrict__ r,
+                                              int64_t bstride, ProjArgs<T> pa,
+                                              const int32_t* __restrict__ blk_active) {
+  __shared__ __align__(16) char smem[8 * WG * sizeof(T)];
+  const int at = blockIdx.x, cb = blockIdx.y;
+  if (blk_active && !blk_active[cb]) return;
+  proj_contract<T, B, WG>(r, bstride, pa, at, cb, smem);
+}
+
+// Stencil pass over one (x-y tile, z-chunk, column block).
+//
+// Krylov vectors are stored per column block as nz + 2*NF planes: NF zero
+// planes below and above the transition region, so that the z-neighbours of
+// every plane are plain loads (the truncation of the T block in z).  The
+// workgroup stages plane iz of its TX x TY tile plus its halo in LDS (two
+// buffers, alternating per plane, one barrier per plane) and keeps, per owned
+// (point, column), the 2*NF+1 z-neighbours in a register queue that rotates
+// instead of shifting: the z-march is unrolled by 2*NF+1 so that the queue slot
+// of each plane is a compile-time index.  Loads for plane iz+1 (queue entry at
+// iz+1+NF, halo ring, r_{n-1}) are issued before plane iz is computed.  Global
+// addresses are a workgroup-uniform 64-bit base plus a 32-bit lane offset.
+// Workgroup ids are remapped so that each XCD owns a contiguous run of
+// (block, z-chunk, tile) indices: tiles that share halos share an L2.
+//
+// FULL: the tile lies inside the x-y plane (no ragged points).
+//
+// MODE_MU uses r^T H r = sum_p r_p (d_p r_p + 2 sum_{axis,k>0} c_k r_{p+k}) (H
+// symmetric; every index pair (p, p+k) of the periodic or truncated axis is
+// counted once), so it needs only the forward neighbours and a one-sided halo;
+// the projector share r^T P D P^T r comes from the contraction (qa).
+template <typename T>
+__device__ __forceinline__ T fmat(T a, T b, T c);
+template <>
+__device__ __forceinline__ double fmat<double>(double a, double b, double c) {
+  return __builtin_fma(a, b, c);
+}
+template <>
+__device__ __forceinline__ float fmat<float>(float a, float b, float c) {
+  return __builtin_fmaf(a, b, c);
+}
+
+template <typename T, int NF, int B, int MODE, int TX, int TY, int NT, bool FULL>
+struct StencilWG {
+  using cT = typename cplx_of<T>::type;
+  static constexpr int W = 2 * NF + 1;
+  static constexpr bool SYM = MODE == MODE_MU;
+  static constexpr int O = SYM ? 0 : NF;  // interior origin inside the LDS tile
+  static constexpr int PX = TX + (SYM ? NF : 2 * NF);
+  static constexpr int PY = TY + (SYM ? NF : 2 * NF);
+  static constexpr int PL = NT / B;  // point lanes
+  static_assert(NT % B == 0 && (TX * TY) % PL == 0, "tile must split evenly over point lanes");
+  static constexpr int OPT = TX * TY / PL;  // owned points per thread per plane
+  static constexpr int RING = PX * PY - TX * TY;
+  static constexpr int HPT = (RING + PL - 1) / PL;  // halo slots per thread
+  // one spare slot per column absorbs the writes of unused halo lanes
+  static constexpr int TILE_BYTES = (PX * PY + 1) * B * (int)sizeof(cT);
+  static constexpr int RED_BYTES = NT * (int)(sizeof(double2) + sizeof(double));
+  // after the two tile buffers: the UPDATE coefficients (ar, ah, ap) of the B columns
+  static constexpr int COEF_OFF = 2 * TILE_BYTES;
+  static constexpr int COEF_BYTES = 3 * B * (int)sizeof(double2);
+  static constexpr int SMEM =
+      COEF_OFF + COEF_BYTES > RED_BYTES ? COEF_OFF + COEF_BYTES : RED_BYTES;
+  static constexpr uint32_t ESZ = sizeof(cT);
+
+  const StencilArgs<T>& a;
+  char* smem;
+  int c, cb, z0, z1, nxy;
+  const char* rbase;  // uniform: this block's vector, first padding plane
+  char* iobase;       // uniform: the UPDATE/APPLY output vector of this block
+  uint32_t pstride;   // bytes per plane
+  uint32_t qoff[OPT], hoff[HPT];  // lane byte offsets inside a plane
+  int iofs[OPT], hl[HPT], gq[OPT];
+  bool val[OPT];
+  cT Q[OPT][W];
+  cT pq[OPT], ph[HPT], pp[OPT];
+  T zr, zi;
+  double2 acc0;
+  double acc1;
+
+  __device__ __forceinline__ StencilWG(const StencilArgs<T>& args, char* sm) : a(args), smem(sm) {}
+
+  __device__ __forceinline__ const cT& ldr(uint32_t plane_pad, uint32_t lane_off) const {
+    return *reinterpret_cast<const cT*>(rbase + plane_pad * pstride + lane_off);
+  }
+
+  // returns false if the workgroup has nothing to do
+  __device__ __forceinline__ bool setup(int lid) {
+    const int t = threadIdx.x, pl = t / B;
+    c = t % B;
+    const int ntile = a.ntx * a.nty;
+    const int tile = lid % ntile;
+    const int zci = (lid / ntile) % a.nzc;
+    cb = lid / (ntile * a.nzc);
+    if (a.blk_active && !a.blk_active[cb]) return false;
+    const int x0 = (tile % a.ntx) * TX, y0 = (tile / a.ntx) * TY;
+    z0 = zci * a.zc;
+    z1 = min(z0 + a.zc, a.nz);
+    nxy = a.nxy;
+    const int nx = a.nx, ny = a.ny;
+    pstride = (uint32_t)nxy * B * ESZ;
+    rbase = reinterpret_cast<const char*>(a.r + (int64_t)cb * a.bstride);
+    iobase = (MODE == MODE_MU) ? nullptr : reinterpret_cast<char*>(a.io + (int64_t)cb * a.bstride);
+#pragma unroll
+    for (int m = 0; m < OPT; ++m) {
+      const int pi = pl + m * PL;
+      const int tx = pi % TX, ty = pi / TX;
+      const int gx = x0 + tx, gy = y0 + ty;
+      val[m] = FULL || (gx < nx && gy < ny);
+      iofs[m] = ((ty + O) * PX + tx + O) * B + c;
+      gq[m] = wrapi(gy, ny) * nx + wrapi(gx, nx);
+      qoff[m] = ((uint32_t)gq[m] * B + c) * ESZ;
+    }
+    // halo slots: full-width bands above and below the interior rows, then the
+    // side pieces of the interior rows; unused lanes write the spare slot
+#pragma unroll
+    for (int i = 0; i < HPT; ++i) {
+      const int h = pl + i * PL;
+      int sx = 0, sy = 0;
+      if (h < (PY - TY) * PX) {
+        const int rr = h / PX;
+        sy = rr < O ? rr : rr + TY;
+        sx = h % PX;
+      } else if (h < RING) {
+        const int q = h - (PY - TY) * PX;
+        sy = O + q / (PX - TX);
+        const int s2 = q % (PX - TX);
+        sx = s2 < O ? s2 : s2 + TX;
+      }
+      hl[i] = (h < RING ? sy * PX + sx : PX * PY) * B + c;
+      const int g = wrapi(y0 + sy - O, ny) * nx + wrapi(x0 + sx - O, nx);
+      hoff[i] = ((uint32_t)g * B + c) * ESZ;
+    }
+    double2 zs = mk(0, 0);
+    if (MODE != MODE_APPLY) {
+      const ColState& cs = a.cols[cb * B + c];
+      zs = cs.zs;
+      if (MODE == MODE_UPDATE && pl == 0) {  // read after the first plane's barrier
+        double2* sc = reinterpret_cast<double2*>(smem + COEF_OFF);
+        sc[c] = cs.ar;
+        sc[B + c] = cs.ah;
+        sc[2 * B + c] = cs.ap;
+      }
+    }
+    zr = (T)zs.x;
+    zi = (T)zs.y;
+    acc0 = mk(0, 0);
+    acc1 = 0.0;
+    // queue planes z0-NF .. z0+NF-1 (padded indices z0 .. z0+2NF-1) into slots
+    // 0 .. 2NF-1 (rotation 0); ragged points keep zeros
+#pragma unroll
+    for (int m = 0; m < OPT; ++m) {
+#pragma unroll
+      for (int d = 0; d < 2 * NF; ++d) {
+        cT v = ldr((uint32_t)(z0 + d), qoff[m]);
+        if (!FULL) {
+          cT zero;
+          zero.x = 0;
+          zero.y = 0;
+          v = csel(val[m], v, zero);
+        }
+        Q[m][d] = v;
+      }
+    }
+    prefetch(z0);
+    return true;
+  }
+
+  // queue entry of plane iz+NF for owned points (a ragged point instead takes
+  // the wrapped value of plane iz, which only fills its LDS slot); r_{n-1} at
+  // plane iz; halo ring of plane iz
+  __device__ __forceinline__ void prefetch(int iz) {
+#pragma unroll
+    for (int m = 0; m < OPT; ++m) {
+      const int zq = (FULL || val[m]) ? iz + 2 * NF : iz + NF;  // padded plane index
+      pq[m] = ldr((uint32_t)zq, qoff[m]);
+      if (MODE == MODE_UPDATE)
+        pp[m] = *reinterpret_cast<const cT*>(iobase + (uint32_t)(iz + NF) * pstride + qoff[m]);
+    }
+#pragma unroll
+    for (int i = 0; i < HPT; ++i) ph[i] = ldr((uint32_t)(iz + NF), hoff[i]);
+  }
+
+  // one plane with queue rotation S: logical queue index d (plane iz-NF+d) lives
+  // in slot (d + S) % W
+  template <int S>
+  __device__ __forceinline__ void step(int iz) {
+    constexpr int snew = (2 * NF + S) % W;
+    constexpr int sctr = (NF + S) % W;
+    cT* lds = reinterpret_cast<cT*>(smem + ((iz - z0) & 1) * TILE_BYTES);
+    // V and the projector range of this plane (the barrier covers part of their latency)
+    const T* vb = a.vloc + (int64_t)iz * nxy;
+    T cv[OPT];
+    int ce0[OPT], ce1[OPT];
+    cT cp[OPT];
+#pragma unroll
+    for (int m = 0; m < OPT; ++m) {
+      cv[m] = vb[gq[m]];
+      if (MODE != MODE_MU) {
+        ce0[m] = ce1[m] = 0;
+        if (a.prow) {  // uniform branch
+          const int32_t* pr = a.prow + (int64_t)iz * nxy + gq[m];
+          ce0[m] = pr[0];
+          ce1[m] = pr[1];
+        }
+      }
+      if (FULL) {
+        Q[m][snew] = pq[m];
+        lds[iofs[m]] = Q[m][sctr];
+      } else {
+        cT zero;
+        zero.x = 0;
+        zero.y = 0;
+        Q[m][snew] = csel(val[m], pq[m], zero);
+        lds[iofs[m]] = csel(val[m], Q[m][sctr], pq[m]);
+      }
+      if (MODE == MODE_UPDATE) cp[m] = pp[m];
+    }
+#pragma unroll
+    for (int i = 0; i < HPT; ++i) lds[hl[i]] = ph[i];
+    // readers of this buffer (plane iz-2) passed the previous plane's barrier
+    // before these writes, so one barrier per plane suffices
+    __syncthreads();
+    if (iz + 1 < z1) prefetch(iz + 1);
+
+#pragma unroll
+    for (int m = 0; m < OPT; ++m) {
+      if (!FULL && !val[m]) continue;
+      const cT ctr = Q[m][sctr];
+      const cT* L = lds + iofs[m];
+      if constexpr (SYM) {
+        // t = (z_s - d_p) r_p - 2 sum_k c_k (r_{p+k x} + r_{p+k y} + r_{p+k z});  mu += r_p t
+        T fr = 0, fi = 0;
+#pragma unroll
+        for (int k = 1; k <= NF; ++k) {
+          const cT zp = Q[m][(NF + k + S) % W];
+          const cT xp = L[k * B];
+          const cT yp = L[k * PX * B];
+          fr = fmat(a.co.cz[k], zp.x, fr);
+          fi = fmat(a.co.cz[k], zp.y, fi);
+          fr = fmat(a.co.cx[k], xp.x, fr);
+          fi = fmat(a.co.cx[k], xp.y, fi);
+          fr = fmat(a.co.cy[k], yp.x, fr);
+          fi = fmat(a.co.cy[k], yp.y, fi);
+        }
+        const T dr = zr - (a.co.c0 + cv[m]);
+        const T tr = fmat(dr, ctr.x, fmat(-zi, ctr.y, (T)-2 * fr));
+        const T ti = fmat(dr, ctr.y, fmat(zi, ctr.x, (T)-2 * fi));
+        const double cr = ctr.x, ci = ctr.y;
+        acc0.x = __builtin_fma(cr, (double)tr, __builtin_fma(-ci, (double)ti, acc0.x));
+        acc0.y = __builtin_fma(cr, (double)ti, __builtin_fma(ci, (double)tr, acc0.y));
+      } else {
+        const T dg = a.co.c0 + cv[m];
+        T hr = dg * ctr.x, hi = dg * ctr.y;
+#pragma unroll
+        for (int k = 1; k <= NF; ++k) {
+          const cT zp = Q[m][(NF + k + S) % W], zm = Q[m][(NF - k + S) % W];
+          hr = fmat(a.co.cz[k], zp.x + zm.x, hr);
+          hi = fmat(a.co.cz[k], zp.y + zm.y, hi);
+        }
+        // x then y neighbours from LDS; the scheduling fence keeps the compiler
+        // from hoisting all 4*NF reads at once (register pressure)
+#pragma unroll
+        for (int k = 1; k <= NF; ++k) {
+          const cT xp = L[k * B], xm = L[-k * B];
+          hr = fmat(a.co.cx[k], xp.x + xm.x, hr);
+          hi = fmat(a.co.cx[k], xp.y + xm.y, hi);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int k = 1; k <= NF; ++k) {
+          const cT yp = L[k * PX * B], ym = L[-k * PX * B];
+          hr = fmat(a.co.cy[k], yp.x + ym.x, hr);
+          hi = fmat(a.co.cy[k], yp.y + ym.y, hi);
+        }
+        for (int e = ce0[m]; e < ce1[m]; ++e) {
+          const cT* dca = a.dc + ((int64_t)cb * a.n_atoms + a.patom[e]) * 4 * B + c;
+          const T* pvv = a.pval + (int64_t)e * 4;
+#pragma unroll
+          for (int l = 0; l < 4; ++l) {
+            const cT d = dca[l * B];
+            hr = fmat(pvv[l], d.x, hr);
+            hi = fmat(pvv[l], d.y, hi);
+          }
+        }
+        cT* op = reinterpret_cast<cT*>(iobase + (uint32_t)(iz + NF) * pstride + qoff[m]);
+        if (MODE == MODE_APPLY) {
+          cT o;
+          o.x = hr;
+          o.y = hi;
+          *op = o;
+        } else {
+          // r_{n+1} = ar r_n + ah (H r_n) + ap r_{n-1} (stored units; ar folds in z_s)
+          const double2* sc = reinterpret_cast<const double2*>(smem + COEF_OFF);
+          const double2 ar = sc[c], ah = sc[B + c], ap = sc[2 * B + c];
+          const double2 rc = to_d(ctr), rp = to_d(cp[m]);
+          const double hx = hr, hy = hi;
+          double2 rn;
+          rn.x = ar.x * rc.x;
+          rn.x = __builtin_fma(-ar.y, rc.y, rn.x);
+          rn.x = __builtin_fma(ah.x, hx, rn.x);
+          rn.x = __builtin_fma(-ah.y, hy, rn.x);
+          rn.x = __builtin_fma(ap.x, rp.x, rn.x);
+          rn.x = __builtin_fma(-ap.y, rp.y, rn.x);
+          rn.y = ar.x * rc.y;
+          rn.y = __builtin_fma(ar.y, rc.x, rn.y);
+          rn.y = __builtin_fma(ah.x, hy, rn.y);
+          rn.y = __builtin_fma(ah.y, hx, rn.y);
+          rn.y = __builtin_fma(ap.x, rp.y, rn.y);
+          rn.y = __builtin_fma(ap.y, rp.x, rn.y);
+          const cT rs = from_d<cT>(rn);
+          *op = rs;
+          const double2 rq = to_d(rs);
+          acc0.x = __builtin_fma(rq.x, rq.x, __builtin_fma(-rq.y, rq.y, acc0.x));
+          acc0.y = __builtin_fma(2.0 * rq.x, rq.y, acc0.y);
+          acc1 = __builtin_fma(rq.x, rq.x, __builtin_fma(rq.y, rq.y, acc1));
+        }
+      }
     }
   }
+
+  // up to W consecutive planes starting at rotation S
+  template <int S>
+  __device__ __forceinline__ void steps(int iz) {
+    if constexpr (S < W) {
+      if (iz < z1) {
+        step<S>(iz);
+        steps<S + 1>(iz + 1);
+      }
+    }
+  }
+
+  __device__ __forceinline__ void march() {
+    for (int iz = z0; iz < z1; iz += W) steps<0>(iz);
+  }
+
+  // fixed-order workgroup reduction over the point lanes of each column
+  __device__ __forceinline__ void reduce_and_store(int slot) {
+    const int t = threadIdx.x, pl = t / B;
+    __syncthreads();  // the tile buffers become reduction scratch
+    double2* s0 = reinterpret_cast<double2*>(smem);
+    double* s1 = reinterpret_cast<double*>(smem + NT * sizeof(double2));
+    s0[t] = acc0;
+    if (MODE == MODE_UPDATE) s1[t] = acc1;
+    __syncthreads();
+#pragma unroll
+    for (int s = PL / 2; s >= 1; s >>= 1) {
+      if (pl < s) {
+        s0[t] = cadd(s0[t], s0[t + s * B]);
+        if (MODE == MODE_UPDATE) s1[t] += s1[t + s * B];
+      }
+      __syncthreads();
+    }
+    if (pl == 0) {
+      const int nwg = a.nzc * a.ntx * a.nty;
+      const int64_t o = ((int64_t)cb * nwg + slot) * B + c;
+      a.part0[o] = s0[t];
+      if (MODE == MODE_UPDATE) a.part1[o] = s1[t];
+    }
+  }
+};
+
+// Stencil pass kernel.  MODE_MU launches additionally carry the projector
+// contraction of r_n: the first nproj_wg workgroups (a multiple of 8, so the
+// XCD slicing of the stencil workgroups is unchanged) each contract one
+// (atom, column block).
+template <typename T, int NF, int B, int MODE, int TX, int TY, int NT, bool FULL>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4)))
+void k_stencil(StencilArgs<T> a) {
+  using SW = StencilWG<T, NF, B, MODE, TX, TY, NT, FULL>;
+  constexpr int PROJ_BYTES = 8 * NT * (int)sizeof(T);
+  __shared__ __align__(16) char smem[SW::SMEM > PROJ_BYTES ? SW::SMEM : PROJ_BYTES];
+  int bid = blockIdx.x;
+  if (MODE == MODE_MU && a.nproj_wg > 0) {
+    if (bid < a.nproj_wg) {
+      const int na = a.proj.n_atoms;
+      if (bid >= na * a.nb) return;
+      const int at = bid % na, cb = bid / na;
+      if (a.blk_active && !a.blk_active[cb]) return;
+      // plane-0 view of the padded vector
+      proj_contract<T, B, NT>(a.r + (int64_t)NF * a.nxy * B, a.bstride, a.proj, at, cb, smem);
+      return;
+    }
+    bid -= a.nproj_wg;
+  }
+  // XCD-aware decode of the logical stencil workgroup id
+  const int ntile = a.ntx * a.nty;
+  const int total = a.nb * a.nzc * ntile;
+  const int lid = (bid % 8) * a.nper + bid / 8;
+  if (lid >= total) return;
+  SW w(a, smem);
+  if (!w.setup(lid)) return;
+  w.march();
+  if (MODE == MODE_APPLY) return;
+  w.reduce_and_store(lid % (a.nzc * ntile));
 }
 
 // ------------------------------------------------------------------ seed alpha (Eq. A5)
@@ -323,13 +636,16 @@ __global__ __launch_bounds__(WG) void k_proj(const typename cplx_of<T>::type* __
 // and the coefficients of the UPDATE pass in stored-buffer units.
 template <int B>
 __global__ __launch_bounds__(WG) void k_alpha(const double2* __restrict__ part, int nwg,
+                                               const double2* __restrict__ qa, int n_atoms,
                                                ColState* __restrict__ cols, int buf_cur,
                                                const int32_t* __restrict__ blk_active) {
   constexpr int PTS = WG / B;
   const int tid = threadIdx.x, c = tid % B, ln = tid / B, cb = blockIdx.x;
   if (!blk_active[cb]) return;
+  // mu^st = sum of the local stencil partials - sum over atoms of r^T P D P^T r
   double2 acc = mk(0, 0);
   for (int w = ln; w < nwg; w += PTS) acc = cadd(acc, part[((int64_t)cb * nwg + w) * B + c]);
+  for (int at = ln; at < n_atoms; at += PTS) acc = csub(acc, qa[((int64_t)cb * n_atoms + at) * B + c]);
   __shared__ double2 sh[WG];
   sh[tid] = acc;
   __syncthreads();
@@ -340,7 +656,7 @@ __global__ __launch_bounds__(WG) void k_alpha(const double2* __restrict__ part, 
   if (ln != 0) return;
   ColState& cs = cols[cb * B + c];
   if (cs.done) {
-    cs.ar = cs.aw = cs.ap = mk(0, 0);
+    cs.ar = cs.ah = cs.ap = mk(0, 0);
     return;
   }
   const double2 s_cur = cs.scale[buf_cur], s_prev = cs.scale[buf_cur ^ 1];
@@ -351,13 +667,15 @@ __global__ __launch_bounds__(WG) void k_alpha(const double2* __restrict__ part, 
   const double2 cc = cdiv(cmul(cs.beta_prev, alpha), cs.alpha_prev);
   if (!(cabs2(denom) > 0.0) || !(cabs2(cs.rho) > 0.0) || !cfinite(alpha) || !cfinite(cc)) {
     cs.breakdown = 1;
-    cs.ar = cs.aw = cs.ap = mk(0, 0);
+    cs.ar = cs.ah = cs.ap = mk(0, 0);
     return;
   }
   cs.alpha = alpha;
   cs.c = cc;
-  cs.ar = cmul(mk(1.0 + cc.x, cc.y), s_cur);
-  cs.aw = cmul(mk(-alpha.x, -alpha.y), s_cur);
+  // r_{n+1} = (1 + c_n) r_n - alpha_n (z_s - H) r_n - c_n r_{n-1}
+  //         = (1 + c_n - alpha_n z_s) r_n + alpha_n H r_n - c_n r_{n-1}
+  cs.ar = cmul(csub(mk(1.0 + cc.x, cc.y), cmul(alpha, cs.zs)), s_cur);
+  cs.ah = cmul(alpha, s_cur);
   cs.ap = cmul(mk(-cc.x, -cc.y), s_prev);
 }
 
@@ -624,7 +942,7 @@ __global__ __launch_bounds__(WG) void k_control(ControlArgs a) {
 // and walks a chunk of the block's active shift list.
 template <typename T, int B, int KCH>
 __global__ __launch_bounds__(WG) void k_shift(const typename cplx_of<T>::type* __restrict__ rnew,
-                                               int64_t N, const int32_t* __restrict__ srow,
+                                               int64_t bstride, const int32_t* __restrict__ srow,
                                                int nS, const int32_t* __restrict__ list,
                                                const int32_t* __restrict__ k5cnt, int K,
                                                const ShiftCoef* __restrict__ coef,
@@ -640,7 +958,7 @@ __global__ __launch_bounds__(WG) void k_shift(const typename cplx_of<T>::type* _
   if (gid >= (int64_t)nS * B) return;
   const int i = (int)(gid / B), c = (int)(gid % B);
   const int64_t row = srow ? (int64_t)srow[i] : (int64_t)i;
-  const double2 rv = to_d(rnew[((int64_t)cb * N + row) * B + c]);
+  const double2 rv = to_d(rnew[(int64_t)cb * bstride + row * B + c]);
   const int32_t* l = list + (int64_t)cb * K;
   for (int e = e0; e < e1; ++e) {
     const int k = l[e];
@@ -656,20 +974,23 @@ __global__ __launch_bounds__(WG) void k_shift(const typename cplx_of<T>::type* _
 }
 
 // ------------------------------------------------------------------ initialisation
-// Krylov buffers r_{-1} = r_0 = e_j (both buffers), for each block column.
+// Krylov buffers r_{-1} = r_0 = e_j (both buffers, padding planes zero), for each
+// block column; bstride = elements per block, pad = points before plane 0.
 template <typename T, int B>
-__global__ void k_init_r(typename cplx_of<T>::type* r0, typename cplx_of<T>::type* r1, int64_t N,
-                         const int32_t* __restrict__ rhs, int R, int nb) {
+__global__ void k_init_r(typename cplx_of<T>::type* r0, typename cplx_of<T>::type* r1,
+                         int64_t bstride, int64_t N, int64_t pad, const int32_t* __restrict__ rhs,
+                         int R, int nb) {
   using cT = typename cplx_of<T>::type;
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t tot = (int64_t)nb * N * B;
+  const int64_t tot = (int64_t)nb * bstride;
   if (gid >= tot) return;
-  const int c = (int)(gid % B);
-  const int64_t pnt = (gid / B) % N;
-  const int cb = (int)(gid / (N * B));
+  const int cb = (int)(gid / bstride);
+  const int64_t w = gid % bstride;
+  const int c = (int)(w % B);
+  const int64_t pnt = w / B - pad;
   const int j = cb * B + c;
   cT v{0, 0};
-  if (j < R && rhs[j] == pnt) v.x = 1;
+  if (j < R && pnt >= 0 && pnt < N && rhs[j] == pnt) v.x = 1;
   r0[gid] = v;
   r1[gid] = v;
 }
@@ -768,26 +1089,26 @@ __global__ void k_gather_out(const double2* __restrict__ x, O* __restrict__ out,
   out[gid] = o;
 }
 
-// one complex128 vector <-> column 0 of a block buffer (for scocg_apply_h)
+// one complex128 vector <-> column 0 of a padded one-block buffer (for scocg_apply_h)
 template <typename T, int B>
 __global__ void k_scatter_col0(const double2* __restrict__ x, typename cplx_of<T>::type* blk,
-                               int64_t N) {
+                               int64_t bstride, int64_t N, int64_t pad) {
   using cT = typename cplx_of<T>::type;
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= N * B) return;
+  if (gid >= bstride) return;
   const int c = (int)(gid % B);
-  const int64_t pnt = gid / B;
+  const int64_t pnt = gid / B - pad;
   cT v{0, 0};
-  if (c == 0) v = from_d<cT>(x[pnt]);
+  if (c == 0 && pnt >= 0 && pnt < N) v = from_d<cT>(x[pnt]);
   blk[gid] = v;
 }
 
 template <typename T, int B>
 __global__ void k_gather_col0(const typename cplx_of<T>::type* __restrict__ blk, double2* y,
-                              int64_t N) {
+                              int64_t N, int64_t pad) {
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= N) return;
-  y[gid] = to_d(blk[gid * B]);
+  y[gid] = to_d(blk[(gid + pad) * B]);
 }
 
 }  // namespace scocg

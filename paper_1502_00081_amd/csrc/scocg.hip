@@ -96,10 +96,11 @@ struct scocg_ctx {
   // last solve
   struct Solve {
     bool ok = false;
-    int B = 0, nb = 0, K = 0, R = 0, nS = 0, nwg = 0, zc = 0, gx = 0, gy = 0;
+    int B = 0, nb = 0, K = 0, R = 0, nS = 0, nwg = 0;
+    StencilGrid g{};
     bool full = false;
     DevBuf r0, r1, z, cols, sh, coef, list, cnt, k5cnt, blk_active, blk_iter, rhs, srow, x, p,
-        dc, part0, part1;
+        dc, qa, part0, part1;
     int32_t* h_flags = nullptr;
     ~Solve() {
       if (h_flags) (void)hipHostFree(h_flags);
@@ -172,17 +173,91 @@ struct Solver {
   scocg_ctx::Solve& S;
   explicit Solver(scocg_ctx& hh, scocg_ctx::Solve& ss) : h(hh), S(ss) {}
 
+  // Krylov vectors: per column block nz + 2*nf planes, nf zero planes on each side
+  int64_t pad_points() const { return (int64_t)h.nf * h.nxy; }
+  int64_t bstride() const { return ((int64_t)h.nz + 2 * h.nf) * h.nxy * B; }
+  // view of a padded vector from its plane 0
+  cT* plane0(cT* base) const { return base + pad_points() * B; }
+
+  // stencil workgroup shapes (see scocg_solve_opts::tile)
+  struct TileCfg { int tx, ty, nt; };
+  static TileCfg tile_cfg(int v) {
+    if constexpr (B == 8) {
+      switch (v) {
+        case 2: return {16, 4, 512};
+        case 3: return {8, 8, 512};
+        case 4: return {16, 8, 512};
+        default: return {16, 8, 1024};
+      }
+    }
+    switch (v) {
+      case 2: return {16, 4, 512};
+      case 3: return {8, 8, 1024};
+      case 4: return {8, 8, 512};
+      default: return {16, 8, 1024};
+    }
+  }
+
+  // tiles and z-chunks: as few z-chunks (each re-reads 2*nf planes to fill its
+  // queue) as still give `target` workgroups
+  StencilGrid plan(int nb, int variant, int zchunk) const {
+    // defaults: the spill-free shapes (complex128: 16x8 tile, 1024 threads;
+    // complex64: 8x8 tile, 1024 threads)
+    if (variant < 1 || variant > 4) variant = B == 8 ? 1 : 3;
+    if (h.nf != 4) variant = 1;
+    const TileCfg tc = tile_cfg(variant);
+    StencilGrid g{};
+    g.variant = variant;
+    g.ntx = (h.nx + tc.tx - 1) / tc.tx;
+    g.nty = (h.ny + tc.ty - 1) / tc.ty;
+    const int64_t per_chunk = (int64_t)nb * g.ntx * g.nty;
+    // about four groups per CU: shorter z-chunks hide latency better than the
+    // re-read of their 2*nf queue planes costs (measured on 48x48x96)
+    const int64_t target = (int64_t)256 * 4096 / tc.nt;
+    int zc = h.nz;
+    if (zchunk > 0) zc = std::min(zchunk, h.nz);
+    else
+      while (zc > 8 && per_chunk * ((h.nz + zc - 1) / zc) < target) zc = (zc + 1) / 2;
+    g.zc = zc;
+    g.nzc = (h.nz + zc - 1) / zc;
+    g.nwg = g.nzc * g.ntx * g.nty;
+    const int64_t total = (int64_t)nb * g.nwg;
+    g.nper = (int)((total + 7) / 8);
+    g.grid = 8 * g.nper;
+    return g;
+  }
+
+  template <int MODE, int NF, int TX, int TY, int NT>
+  void launch_v(const StencilArgs<T>& a, int grid) {
+    // interior tiles only when the tile divides the plane
+    if (h.nx % TX == 0 && h.ny % TY == 0 && NF == 4)
+      hipLaunchKernelGGL((k_stencil<T, NF, B, MODE, TX, TY, NT, true>), dim3(grid + a.nproj_wg),
+                         dim3(NT), 0, h.stream, a);
+    else
+      hipLaunchKernelGGL((k_stencil<T, NF, B, MODE, TX, TY, NT, false>), dim3(grid + a.nproj_wg),
+                         dim3(NT), 0, h.stream, a);
+  }
+
+  // MODE_MU with qa != null also contracts the projectors (into dc and qa)
   template <int MODE>
   void launch_stencil(const cT* r, cT* io, const ColState* cols, const int32_t* blk_active,
-                      int nb, int gx, int gy, int zc, double2* part0, double* part1,
-                      const cT* dc) {
+                      int nb, const StencilGrid& g, double2* part0, double* part1, cT* dc,
+                      double2* qa = nullptr) {
     StencilArgs<T> a{};
+    a.bstride = bstride();
+    if (MODE == MODE_MU && qa && h.n_atoms) {
+      a.nproj_wg = (h.n_atoms * nb + 7) / 8 * 8;
+      a.proj = proj_args(dc, qa);
+    }
     a.r = r;
     a.io = io;
     a.vloc = h.vloc.as<T>();
     a.co = make_coefs<T>(h);
     a.nx = h.nx; a.ny = h.ny; a.nz = h.nz; a.nxy = h.nxy;
-    a.zc = zc;
+    a.ntx = g.ntx; a.nty = g.nty;
+    a.zc = g.zc; a.nzc = g.nzc;
+    a.nb = nb;
+    a.nper = g.nper;
     a.prow = h.n_atoms ? h.prow.as<int32_t>() : nullptr;
     a.patom = h.patom.as<int32_t>();
     a.pval = h.pval.as<T>();
@@ -192,31 +267,49 @@ struct Solver {
     a.blk_active = blk_active;
     a.part0 = part0;
     a.part1 = part1;
-    dim3 grid(gx, gy, nb);
     switch (h.nf) {
-      case 1: hipLaunchKernelGGL((k_stencil<T, 1, B, MODE>), grid, dim3(WG), 0, h.stream, a); break;
-      case 2: hipLaunchKernelGGL((k_stencil<T, 2, B, MODE>), grid, dim3(WG), 0, h.stream, a); break;
-      case 3: hipLaunchKernelGGL((k_stencil<T, 3, B, MODE>), grid, dim3(WG), 0, h.stream, a); break;
-      default: hipLaunchKernelGGL((k_stencil<T, 4, B, MODE>), grid, dim3(WG), 0, h.stream, a); break;
+      case 1: launch_v<MODE, 1, 16, 8, 1024>(a, g.grid); break;
+      case 2: launch_v<MODE, 2, 16, 8, 1024>(a, g.grid); break;
+      case 3: launch_v<MODE, 3, 16, 8, 1024>(a, g.grid); break;
+      default:
+        if constexpr (B == 8) {
+          switch (g.variant) {
+            case 2: launch_v<MODE, 4, 16, 4, 512>(a, g.grid); break;
+            case 3: launch_v<MODE, 4, 8, 8, 512>(a, g.grid); break;
+            case 4: launch_v<MODE, 4, 16, 8, 512>(a, g.grid); break;
+            default: launch_v<MODE, 4, 16, 8, 1024>(a, g.grid); break;
+          }
+        } else {
+          switch (g.variant) {
+            case 2: launch_v<MODE, 4, 16, 4, 512>(a, g.grid); break;
+            case 3: launch_v<MODE, 4, 8, 8, 1024>(a, g.grid); break;
+            case 4: launch_v<MODE, 4, 8, 8, 512>(a, g.grid); break;
+            default: launch_v<MODE, 4, 16, 8, 1024>(a, g.grid); break;
+          }
+        }
     }
     KCHK();
   }
 
-  void launch_proj(const cT* r, int nb, cT* dc, const int32_t* blk_active) {
-    if (!h.n_atoms) return;
-    hipLaunchKernelGGL((k_proj<T, B>), dim3(h.n_atoms, nb), dim3(WG), 0, h.stream, r, h.N,
-                       h.aptr.as<int32_t>(), h.aidx.as<int32_t>(), h.aval.as<T>(),
-                       h.aD.as<T>(), h.n_proj, h.n_atoms, dc, blk_active);
-    KCHK();
+  ProjArgs<T> proj_args(cT* dc, double2* qa) const {
+    ProjArgs<T> pa{};
+    pa.aptr = h.aptr.as<int32_t>();
+    pa.aidx = h.aidx.as<int32_t>();
+    pa.aval = h.aval.as<T>();
+    pa.aD = h.aD.as<T>();
+    pa.n_proj = h.n_proj;
+    pa.n_atoms = h.n_atoms;
+    pa.dc = dc;
+    pa.qa = qa;
+    return pa;
   }
 
-  // grid of the stencil pass: PTS x-y points per workgroup, zc planes per workgroup
-  void plan_grid(int nb, int& gx, int& gy, int& zc) const {
-    constexpr int PTS = WG / B;
-    gx = (int)nblocks(h.nxy, PTS);
-    zc = 32;
-    while (zc > 4 && (int64_t)gx * nblocks(h.nz, zc) * nb < 4096) zc /= 2;
-    gy = (int)nblocks(h.nz, zc);
+  // r: padded vector base
+  void launch_proj(cT* r, int nb, cT* dc, const int32_t* blk_active) {
+    if (!h.n_atoms) return;
+    hipLaunchKernelGGL((k_proj<T, B>), dim3(h.n_atoms, nb), dim3(WG), 0, h.stream, plane0(r),
+                       bstride(), proj_args(dc, nullptr), blk_active);
+    KCHK();
   }
 
   // ev: null, or 2*SCOCG_K_FAMILIES events recorded around the launches of this iteration
@@ -228,20 +321,17 @@ struct Solver {
     cT* rc = (cur ? S.r1 : S.r0).template as<cT>();
     cT* rn = (cur ? S.r0 : S.r1).template as<cT>();
     const int32_t* act = S.blk_active.as<int32_t>();
-    mark(ev, SCOCG_K_PROJ, 0);
-    launch_proj(rc, S.nb, S.dc.as<cT>(), act);
-    mark(ev, SCOCG_K_PROJ, 1);
     mark(ev, SCOCG_K_MU, 0);
-    launch_stencil<MODE_MU>(rc, nullptr, S.cols.as<ColState>(), act, S.nb, S.gx, S.gy, S.zc,
-                            S.part0.as<double2>(), nullptr, S.dc.as<cT>());
+    launch_stencil<MODE_MU>(rc, nullptr, S.cols.as<ColState>(), act, S.nb, S.g,
+                            S.part0.as<double2>(), nullptr, S.dc.as<cT>(), S.qa.as<double2>());
     mark(ev, SCOCG_K_MU, 1);
     mark(ev, SCOCG_K_ALPHA, 0);
     hipLaunchKernelGGL((k_alpha<B>), dim3(S.nb), dim3(WG), 0, h.stream, S.part0.as<double2>(),
-                       S.nwg, S.cols.as<ColState>(), cur, act);
+                       S.nwg, S.qa.as<double2>(), h.n_atoms, S.cols.as<ColState>(), cur, act);
     KCHK();
     mark(ev, SCOCG_K_ALPHA, 1);
     mark(ev, SCOCG_K_UPDATE, 0);
-    launch_stencil<MODE_UPDATE>(rc, rn, S.cols.as<ColState>(), act, S.nb, S.gx, S.gy, S.zc,
+    launch_stencil<MODE_UPDATE>(rc, rn, S.cols.as<ColState>(), act, S.nb, S.g,
                                 S.part0.as<double2>(), S.part1.as<double>(), S.dc.as<cT>());
     mark(ev, SCOCG_K_UPDATE, 1);
     ControlArgs ca{};
@@ -271,7 +361,7 @@ struct Solver {
     constexpr int KCH = 16;
     const int64_t rows = (int64_t)S.nS * B;
     dim3 g5(nblocks(rows, WG), nblocks(S.K, KCH), S.nb);
-    hipLaunchKernelGGL((k_shift<T, B, KCH>), g5, dim3(WG), 0, h.stream, rn, h.N,
+    hipLaunchKernelGGL((k_shift<T, B, KCH>), g5, dim3(WG), 0, h.stream, plane0(rn), bstride(),
                        S.full ? nullptr : S.srow.as<int32_t>(), S.nS,
                        S.list.as<int32_t>() + (int64_t)par * S.nb * S.K, S.k5cnt.as<int32_t>(),
                        S.K, S.coef.as<ShiftCoef>(), S.x.as<double2>(), S.p.as<cT>());
@@ -304,9 +394,9 @@ struct Solver {
     DevBuf zk;
     upload(zk, zh, st);
     // state
-    plan_grid(nb, S.gx, S.gy, S.zc);
-    S.nwg = S.gx * S.gy;
-    const size_t vec = (size_t)nb * h.N * B * sizeof(cT);
+    S.g = plan(nb, o.tile, o.zchunk);
+    S.nwg = S.g.nwg;
+    const size_t vec = (size_t)nb * bstride() * sizeof(cT);
     S.r0.alloc(vec);
     S.r1.alloc(vec);
     const size_t nkb = (size_t)nb * K * B;
@@ -323,6 +413,7 @@ struct Solver {
     S.x.alloc(xp * sizeof(double2));
     S.p.alloc(xp * sizeof(cT));
     S.dc.alloc((size_t)std::max(h.n_atoms, 1) * nb * 4 * B * sizeof(cT));
+    S.qa.alloc((size_t)std::max(h.n_atoms, 1) * nb * B * sizeof(double2));
     S.part0.alloc((size_t)nb * S.nwg * B * sizeof(double2));
     S.part1.alloc((size_t)nb * S.nwg * B * sizeof(double));
     if (!S.h_flags) HIPCHK(hipHostMalloc((void**)&S.h_flags, sizeof(int32_t) * 65536));
@@ -332,8 +423,9 @@ struct Solver {
     HIPCHK(hipEventCreate(&e1));
     HIPCHK(hipEventRecord(e0, st));
     const int seed0 = o.init_seed < 0 ? K / 2 : o.init_seed;
-    hipLaunchKernelGGL((k_init_r<T, B>), dim3(nblocks((int64_t)nb * h.N * B, WG)), dim3(WG), 0,
-                       st, S.r0.as<cT>(), S.r1.as<cT>(), h.N, S.rhs.as<int32_t>(), R, nb);
+    hipLaunchKernelGGL((k_init_r<T, B>), dim3(nblocks((int64_t)nb * bstride(), WG)), dim3(WG), 0,
+                       st, S.r0.as<cT>(), S.r1.as<cT>(), bstride(), h.N, pad_points(),
+                       S.rhs.as<int32_t>(), R, nb);
     KCHK();
     hipLaunchKernelGGL((k_init_xp<T, B>), dim3(nblocks((int64_t)xp, WG)), dim3(WG), 0, st,
                        S.x.as<double2>(), S.p.as<cT>(), S.full ? nullptr : S.srow.as<int32_t>(),
@@ -381,7 +473,7 @@ struct Solver {
       if (o.timing) {
         for (int s2 = 0; s2 < poll; ++s2)
           for (int f = 0; f < SCOCG_K_FAMILIES; ++f) {
-            if (f == SCOCG_K_PROJ && !h.n_atoms) continue;
+            if (f == SCOCG_K_PROJ) continue;  // fused into the MU launch
             float t = 0.f;
             hipEvent_t* e = ev_of(s2);
             HIPCHK(hipEventElapsedTime(&t, e[2 * f], e[2 * f + 1]));
@@ -451,6 +543,7 @@ struct Solver {
     S.part0.release();
     S.part1.release();
     S.dc.release();
+    S.qa.release();
     S.ok = true;
     return rc;
   }
@@ -462,19 +555,19 @@ void apply_h_impl(scocg_ctx& h, const void* x, void* y) {
   scocg_ctx::Solve tmp;
   Solver<T, B> sv(h, tmp);
   DevBuf blk, out, dc;
-  blk.alloc((size_t)h.N * B * sizeof(cT));
-  out.alloc((size_t)h.N * B * sizeof(cT));
+  blk.alloc((size_t)sv.bstride() * sizeof(cT));
+  out.alloc((size_t)sv.bstride() * sizeof(cT));
   dc.alloc((size_t)std::max(h.n_atoms, 1) * 4 * B * sizeof(cT));
-  hipLaunchKernelGGL((k_scatter_col0<T, B>), dim3(nblocks(h.N * B, WG)), dim3(WG), 0, h.stream,
-                     static_cast<const double2*>(x), blk.as<cT>(), h.N);
+  hipLaunchKernelGGL((k_scatter_col0<T, B>), dim3(nblocks(sv.bstride(), WG)), dim3(WG), 0,
+                     h.stream, static_cast<const double2*>(x), blk.as<cT>(), sv.bstride(), h.N,
+                     sv.pad_points());
   KCHK();
   sv.launch_proj(blk.as<cT>(), 1, dc.as<cT>(), nullptr);
-  int gx, gy, zc;
-  sv.plan_grid(1, gx, gy, zc);
-  sv.template launch_stencil<MODE_APPLY>(blk.as<cT>(), out.as<cT>(), nullptr, nullptr, 1, gx, gy,
-                                         zc, nullptr, nullptr, dc.as<cT>());
+  const auto g = sv.plan(1, 0, 0);
+  sv.template launch_stencil<MODE_APPLY>(blk.as<cT>(), out.as<cT>(), nullptr, nullptr, 1, g,
+                                         nullptr, nullptr, dc.as<cT>());
   hipLaunchKernelGGL((k_gather_col0<T, B>), dim3(nblocks(h.N, WG)), dim3(WG), 0, h.stream,
-                     out.as<cT>(), static_cast<double2*>(y), h.N);
+                     out.as<cT>(), static_cast<double2*>(y), h.N, sv.pad_points());
   KCHK();
   HIPCHK(hipStreamSynchronize(h.stream));
 }
@@ -516,8 +609,11 @@ int scocg_create(const scocg_grid* g, const double* coef, const double* vloc, in
     require(g != nullptr && coef != nullptr && vloc != nullptr, "grid, coef or vloc is NULL");
     require(g->nf >= 1 && g->nf <= 4, "nf must be 1..4");
     require(g->nx >= g->nf && g->ny >= g->nf && g->nz >= 1, "need nx, ny >= nf and nz >= 1");
-    require(g->nx * g->ny <= (1 << 30) && g->nx * g->ny * g->nz <= ((int64_t)1 << 31) / 32,
-            "grid too large for 32-bit point indices");
+    // one padded column block ((nz + 2 nf) planes x 128 bytes per point) must be
+    // addressable with 32-bit byte offsets
+    require(g->nx * g->ny <= (1 << 30) &&
+                (g->nz + 2 * g->nf) * g->nx * g->ny * 128 < ((int64_t)1 << 32),
+            "grid too large for 32-bit offsets within a column block");
     require(g->n_proj >= 0 && g->n_proj <= 4, "n_proj must be 0..4");
     require(precision == SCOCG_FP64 || precision == SCOCG_MIXED, "unknown precision");
     require(n_atoms >= 0, "n_atoms < 0");

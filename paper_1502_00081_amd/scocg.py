@@ -34,7 +34,8 @@ class Grid(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int64), ("init_seed", C.c_int32),
                 ("seed_switch", C.c_int32), ("full", C.c_int32), ("refine", C.c_int32),
-                ("poll_every", C.c_int32), ("use_graph", C.c_int32), ("timing", C.c_int32)]
+                ("poll_every", C.c_int32), ("use_graph", C.c_int32), ("timing", C.c_int32),
+                ("tile", C.c_int32), ("zchunk", C.c_int32)]
 
 
 class Report(C.Structure):
@@ -118,7 +119,8 @@ class Handle:
         self.last = None
 
     def solve(self, z, rhs_idx, s_idx=None, tol=1e-10, max_iter=100000, init_seed=-1,
-              seed_switch=True, full=False, refine=0, poll_every=0, use_graph=False, timing=False):
+              seed_switch=True, full=False, refine=0, poll_every=0, use_graph=False, timing=False,
+              tile=0, zchunk=0):
         """scocg_solve; returns (rc, report dict with [K, R] arrays)."""
         lib = load()
         z = _c(z, np.complex128)
@@ -131,7 +133,7 @@ class Handle:
             nS = sp.size
         o = SolveOpts(float(tol), int(max_iter), int(init_seed), int(bool(seed_switch)),
                       int(bool(full)), int(refine), int(poll_every), int(bool(use_graph)),
-                      int(bool(timing)))
+                      int(bool(timing)), int(tile), int(zchunk))
         iters = np.zeros((K, R), np.int64)
         est = np.zeros((K, R))
         tres = np.zeros((K, R))

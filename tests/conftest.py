@@ -18,6 +18,11 @@ def _announce_gpu_case(request):
     """Name every GPU case on the real stderr before it touches the device, so a
     run that ends abruptly still shows which case was running."""
     if request.node.get_closest_marker("gpu"):
-        sys.__stderr__.write(f"[gpu-case] start {request.node.nodeid}\n")
+        line = f"[gpu-case] start {request.node.nodeid}\n"
+        path = os.environ.get("SCOCG_TEST_PROGRESS")
+        if path:
+            with open(path, "a") as f:
+                f.write(line)
+        sys.__stderr__.write(line)
         sys.__stderr__.flush()
     yield
