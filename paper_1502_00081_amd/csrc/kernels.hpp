@@ -707,11 +707,16 @@ struct ControlArgs {
 //   alpha^(k)_n = pi_n/pi_{n+1} alpha_n,  beta^(k)_n = (pi_n/pi_{n+1})^2 beta_n  (Eqs. A9-A10)
 //   freeze (k, j) once ||r_{n+1}|| / |pi_{n+1}| <= tol ||b||; compact the active list;
 //   seed switch to the active shift of smallest |pi_{n+1}| once the seed froze (Eq. A13).
-// Thread t always serves column t % B (WG is a multiple of B), so every
-// per-column reduction is one fixed-order tree over the WG/B lanes of that column.
+// Thread t always serves column t % B (CT is a multiple of B), so every
+// per-column reduction is one fixed-order tree over the CT/B lanes of that
+// column.  Activity flags and |pi_{n+1}| of the block live in dynamic LDS
+// ([K][B] each) between the phases; the compaction uses wave ballots.
+constexpr int CT = 512;  // threads of the control kernel
+
 template <int B>
-__global__ __launch_bounds__(WG) void k_control(ControlArgs a) {
-  constexpr int PTS = WG / B;
+__global__ __launch_bounds__(CT) void k_control(ControlArgs a) {
+  constexpr int PL = CT / B;
+  constexpr int NWAVE = CT / 64;
   const int tid = threadIdx.x, c = tid % B, ln = tid / B, cb = blockIdx.x;
   if (!a.blk_active[cb]) {
     if (tid == 0) a.k5cnt[cb] = 0;
@@ -719,21 +724,24 @@ __global__ __launch_bounds__(WG) void k_control(ControlArgs a) {
   }
   const int K = a.K;
   const int n = a.blk_iter[cb];
-  __shared__ double2 sh_rho[WG];
-  __shared__ double sh_nu[WG];
-  __shared__ double s_best[WG];
-  __shared__ int s_bestk[WG];
-  __shared__ int s_scan[WG];
+  extern __shared__ __align__(16) char dyn[];
+  double* pim = reinterpret_cast<double*>(dyn);                     // [K][B] |pi_{n+1}|
+  unsigned char* act = reinterpret_cast<unsigned char*>(dyn + (size_t)K * B * sizeof(double));
+  __shared__ double2 sh_rho[CT];
+  __shared__ double sh_nu[CT];
+  __shared__ int s_k[CT];
   __shared__ double2 s_alpha[B], s_beta[B], s_c[B], s_zs[B], s_fn[B], s_fc[B];
   __shared__ double s_nrm[B];
   __shared__ int s_live[B], s_cnt_col[B], s_argmin[B], s_sw[B];
-  __shared__ int s_total;
+  __shared__ int s_wsum[NWAVE];
+  __shared__ double2 s_rhon[B];
+  __shared__ int s_any_sw;
 
   // 1. reduce rho_{n+1} and ||r_{n+1}||^2 partials
   {
     double2 ra = mk(0, 0);
     double na = 0.0;
-    for (int w = ln; w < a.nwg; w += PTS) {
+    for (int w = ln; w < a.nwg; w += PL) {
       const int64_t o = ((int64_t)cb * a.nwg + w) * B + c;
       ra = cadd(ra, a.part_rho[o]);
       na += a.part_nu[o];
@@ -742,7 +750,7 @@ __global__ __launch_bounds__(WG) void k_control(ControlArgs a) {
     sh_nu[tid] = na;
   }
   __syncthreads();
-  for (int s = PTS / 2; s >= 1; s >>= 1) {
+  for (int s = PL / 2; s >= 1; s >>= 1) {
     if (ln < s) {
       sh_rho[tid] = cadd(sh_rho[tid], sh_rho[tid + s * B]);
       sh_nu[tid] += sh_nu[tid + s * B];
@@ -754,6 +762,7 @@ __global__ __launch_bounds__(WG) void k_control(ControlArgs a) {
     cs.scale[a.buf_new] = mk(1.0, 0.0);  // r_{n+1} was just written unscaled
     const int live = !cs.done && !cs.breakdown;
     s_live[tid] = live;
+    s_rhon[tid] = sh_rho[tid];
     if (live) {
       s_beta[tid] = cdiv(sh_rho[tid], cs.rho);
       s_alpha[tid] = cs.alpha;
@@ -761,6 +770,7 @@ __global__ __launch_bounds__(WG) void k_control(ControlArgs a) {
       s_zs[tid] = cs.zs;
       s_nrm[tid] = sqrt(sh_nu[tid]) / cs.bnorm;
     }
+    if (tid == 0) s_any_sw = 0;
   }
   __syncthreads();
 
@@ -771,7 +781,7 @@ __global__ __launch_bounds__(WG) void k_control(ControlArgs a) {
   const int ncur = a.cnt[par * gridDim.x + cb];
   const bool live_c = s_live[c];
   const bool brk_c = a.cols[cb * B + c].breakdown;
-  for (int e = ln; e < ncur; e += PTS) {
+  for (int e = ln; e < ncur; e += PL) {
     const int k = lcur[e];
     const int64_t o = ((int64_t)cb * K + k) * B + c;
     ShiftState st = a.sh[o];
@@ -809,30 +819,33 @@ __global__ __launch_bounds__(WG) void k_control(ControlArgs a) {
       a.sh[o] = st;
     }
     a.coef[o] = cf;
+    act[k * B + c] = (unsigned char)st.active;
+    pim[k * B + c] = cabsd(st.pi);
   }
   __syncthreads();
 
-  // 3. stable compaction of the shifts still active in any column of the block
+  // 3. stable compaction of the shifts still active in any column of the block:
+  //    rank inside each wave by ballot, wave offsets by a serial prefix over waves
+  const int lane = tid & 63, wave = tid >> 6;
   int base = 0;
-  for (int e0 = 0; e0 < ncur; e0 += WG) {
+  for (int e0 = 0; e0 < ncur; e0 += CT) {
     const int e = e0 + tid;
     int keep = 0, k = -1;
     if (e < ncur) {
       k = lcur[e];
-      for (int cc = 0; cc < B; ++cc) keep |= a.sh[((int64_t)cb * K + k) * B + cc].active;
+#pragma unroll
+      for (int cc = 0; cc < B; ++cc) keep |= act[k * B + cc];
     }
-    s_scan[tid] = keep;
+    const unsigned long long m = __ballot(keep);
+    const int rank = __popcll(m & ((1ull << lane) - 1ull));
+    if (lane == 0) s_wsum[wave] = __popcll(m);
     __syncthreads();
-    for (int off = 1; off < WG; off <<= 1) {  // inclusive scan
-      const int v = tid >= off ? s_scan[tid - off] : 0;
-      __syncthreads();
-      s_scan[tid] += v;
-      __syncthreads();
-    }
-    if (keep) lnext[base + s_scan[tid] - 1] = k;
-    if (tid == WG - 1) s_total = s_scan[tid];
-    __syncthreads();
-    base += s_total;
+    int off = base;
+    for (int w = 0; w < wave; ++w) off += s_wsum[w];
+    if (keep) lnext[off + rank] = k;
+    int tot = 0;
+    for (int w = 0; w < NWAVE; ++w) tot += s_wsum[w];
+    base += tot;
     __syncthreads();
   }
   const int nnext = base;
@@ -841,37 +854,37 @@ __global__ __launch_bounds__(WG) void k_control(ControlArgs a) {
   {
     double best = INFINITY;
     int bestk = 0x7fffffff, cnt = 0;
-    for (int e = ln; e < nnext; e += PTS) {
+    for (int e = ln; e < nnext; e += PL) {
       const int k = lnext[e];
-      const ShiftState& st = a.sh[((int64_t)cb * K + k) * B + c];
-      if (st.active) {
+      if (act[k * B + c]) {
         ++cnt;
-        const double m = cabsd(st.pi);
-        if (m < best || (m == best && k < bestk)) { best = m; bestk = k; }
+        const double mm = pim[k * B + c];
+        if (mm < best || (mm == best && k < bestk)) { best = mm; bestk = k; }
       }
     }
-    s_best[tid] = best;
-    s_bestk[tid] = bestk;
-    s_scan[tid] = cnt;
+    sh_nu[tid] = best;
+    s_k[tid] = bestk;
+    sh_rho[tid].x = cnt;
   }
   __syncthreads();
-  for (int s = PTS / 2; s >= 1; s >>= 1) {
+  for (int s = PL / 2; s >= 1; s >>= 1) {
     if (ln < s) {
-      const double b2 = s_best[tid + s * B];
-      const int k2 = s_bestk[tid + s * B];
-      if (b2 < s_best[tid] || (b2 == s_best[tid] && k2 < s_bestk[tid])) {
-        s_best[tid] = b2;
-        s_bestk[tid] = k2;
+      const double b2 = sh_nu[tid + s * B];
+      const int k2 = s_k[tid + s * B];
+      if (b2 < sh_nu[tid] || (b2 == sh_nu[tid] && k2 < s_k[tid])) {
+        sh_nu[tid] = b2;
+        s_k[tid] = k2;
       }
-      s_scan[tid] += s_scan[tid + s * B];
+      sh_rho[tid].x += sh_rho[tid + s * B].x;
     }
     __syncthreads();
   }
+  int cnt_c = 0, argmin_c = 0;
   if (tid < B) {
-    s_cnt_col[tid] = s_scan[tid];
-    s_argmin[tid] = s_bestk[tid];
+    cnt_c = (int)sh_rho[tid].x;
+    argmin_c = s_k[tid];
   }
-  __syncthreads();
+  __syncthreads();  // sh_rho is reused below
 
   // 5. seed switch (Eq. A13) and column bookkeeping; stored buffers are rescaled
   //    lazily through ColState::scale (true r = scale * stored r).
@@ -881,10 +894,9 @@ __global__ __launch_bounds__(WG) void k_control(ControlArgs a) {
     int sw = -1;
     if (s_live[tid]) {
       double2 alpha = s_alpha[tid], beta = s_beta[tid];
-      double2 rho_new = sh_rho[tid];
+      double2 rho_new = s_rhon[tid];
       const ShiftState& sst = a.sh[((int64_t)cb * K + cs.seed) * B + tid];
-      const int ntot = s_cnt_col[tid];
-      if (a.seed_switch && !sst.active && ntot > 0 && !last) sw = s_argmin[tid];
+      if (a.seed_switch && !sst.active && cnt_c > 0 && !last) sw = argmin_c;
       if (sw >= 0) {
         const ShiftState& t = a.sh[((int64_t)cb * K + sw) * B + tid];
         const double2 fn = t.pi, fc = t.pi_prev;  // pi^{(s,s~)}_{n+1}, pi^{(s,s~)}_n
@@ -899,12 +911,13 @@ __global__ __launch_bounds__(WG) void k_control(ControlArgs a) {
         cs.nswitch += 1;
         s_fn[tid] = fn;
         s_fc[tid] = fc;
+        s_any_sw = 1;
       }
       cs.rho = rho_new;
       cs.alpha_prev = alpha;
       cs.beta_prev = beta;
       cs.iters = n + 1;
-      if (ntot == 0 || last) cs.done = 1;
+      if (cnt_c == 0 || last) cs.done = 1;
     } else if (cs.breakdown) {
       cs.done = 1;
     }
@@ -912,17 +925,19 @@ __global__ __launch_bounds__(WG) void k_control(ControlArgs a) {
   }
   __syncthreads();
   // rebase pi of the active shifts of switched columns; max-iteration cut-off
-  for (int e = ln; e < nnext; e += PTS) {
-    const int k = lnext[e];
-    ShiftState& st = a.sh[((int64_t)cb * K + k) * B + c];
-    if (!st.active) continue;
-    if (last) {
-      st.active = 0;
-      st.status = ST_MAXITER;
-      st.iters = n + 1;
-    } else if (s_sw[c] >= 0) {
-      st.pi = cdiv(st.pi, s_fn[c]);
-      st.pi_prev = cdiv(st.pi_prev, s_fc[c]);
+  if (s_any_sw || last) {
+    for (int e = ln; e < nnext; e += PL) {
+      const int k = lnext[e];
+      ShiftState& st = a.sh[((int64_t)cb * K + k) * B + c];
+      if (!st.active) continue;
+      if (last) {
+        st.active = 0;
+        st.status = ST_MAXITER;
+        st.iters = n + 1;
+      } else if (s_sw[c] >= 0) {
+        st.pi = cdiv(st.pi, s_fn[c]);
+        st.pi_prev = cdiv(st.pi_prev, s_fc[c]);
+      }
     }
   }
   __syncthreads();

@@ -312,6 +312,9 @@ struct Solver {
     KCHK();
   }
 
+  // dynamic LDS of k_control: |pi| (double) and an activity byte per (shift, column)
+  static size_t control_lds(int K) { return (size_t)K * B * (sizeof(double) + 1); }
+
   // ev: null, or 2*SCOCG_K_FAMILIES events recorded around the launches of this iteration
   void mark(hipEvent_t* ev, int fam, int end) {
     if (ev) HIPCHK(hipEventRecord(ev[2 * fam + end], h.stream));
@@ -354,11 +357,11 @@ struct Solver {
     ca.max_iter = o.max_iter;
     ca.seed_switch = o.seed_switch;
     mark(ev, SCOCG_K_CONTROL, 0);
-    hipLaunchKernelGGL((k_control<B>), dim3(S.nb), dim3(WG), 0, h.stream, ca);
+    hipLaunchKernelGGL((k_control<B>), dim3(S.nb), dim3(CT), control_lds(S.K), h.stream, ca);
     KCHK();
     mark(ev, SCOCG_K_CONTROL, 1);
     mark(ev, SCOCG_K_SHIFT, 0);
-    constexpr int KCH = 16;
+    constexpr int KCH = 4;
     const int64_t rows = (int64_t)S.nS * B;
     dim3 g5(nblocks(rows, WG), nblocks(S.K, KCH), S.nb);
     hipLaunchKernelGGL((k_shift<T, B, KCH>), g5, dim3(WG), 0, h.stream, plane0(rn), bstride(),
@@ -372,6 +375,10 @@ struct Solver {
   int run(int K, const double* z, int R, const int64_t* rhs_idx, int nS_in, const int64_t* s_idx,
           const scocg_solve_opts& o, scocg_report* rep) {
     require((R + B - 1) / B <= 65536, "too many column blocks");
+    require(control_lds(K) <= 128 * 1024, "too many energies for one column block (K*B)");
+    HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_control<B>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)control_lds(K)));
     S.B = B;
     S.K = K;
     S.R = R;
