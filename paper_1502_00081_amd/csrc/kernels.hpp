@@ -1029,11 +1029,13 @@ __global__ void k_init_xp(double2* x, typename cplx_of<T>::type* p, const int32_
   p[gid] = v;
 }
 
+// z: [K] energies shared by every column, or (zpc != null, K == 1) one energy per
+// column zpc[cb*B + c].
 template <int B>
 __global__ void k_init_state(ColState* cols, ShiftState* sh, ShiftCoef* coef, double2* zcol,
-                             const double2* __restrict__ z, int K, int nb, int R, int seed0,
-                             int32_t* list, int32_t* cnt, int32_t* k5cnt, int32_t* blk_active,
-                             int32_t* blk_iter) {
+                             const double2* __restrict__ z, const double2* __restrict__ zpc,
+                             int K, int nb, int R, int seed0, int32_t* list, int32_t* cnt,
+                             int32_t* k5cnt, int32_t* blk_active, int32_t* blk_iter) {
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t tot = (int64_t)nb * K * B;
   if (gid < tot) {
@@ -1053,7 +1055,7 @@ __global__ void k_init_state(ColState* cols, ShiftState* sh, ShiftCoef* coef, do
     ShiftCoef cf{};
     cf.upd = 0;
     coef[gid] = cf;
-    zcol[gid] = z[k];
+    zcol[gid] = zpc ? zpc[cb * B + c] : z[k];
     if (c == 0) {
       list[(int64_t)cb * K + k] = k;
       list[((int64_t)nb + cb) * K + k] = k;
@@ -1067,7 +1069,7 @@ __global__ void k_init_state(ColState* cols, ShiftState* sh, ShiftCoef* coef, do
     cs.beta_prev = mk(0, 0);
     cs.alpha = mk(0, 0);
     cs.c = mk(0, 0);
-    cs.zs = z[seed0];
+    cs.zs = zpc ? zpc[j] : z[seed0];
     cs.scale[0] = mk(1, 0);
     cs.scale[1] = mk(1, 0);
     cs.bnorm = 1.0;
@@ -1084,6 +1086,208 @@ __global__ void k_init_state(ColState* cols, ShiftState* sh, ShiftCoef* coef, do
     blk_active[cb] = any;
     blk_iter[cb] = 0;
   }
+}
+
+// ------------------------------------------------------------------ FP64 true residual
+// t = b - (z - H) x in FP64 for x in the full-storage layout [nblk][N][B] (nblk =
+// nb*K; block kb = cb*K + k holds x^(k) of columns cb*B..cb*B+B-1); b = e_j for a
+// unit right-hand side (rhs != null) or a dense vector brhs [nblk][N][B] (null:
+// zero).  One thread per (point, column), neighbours straight from memory (a
+// one-off pass, not part of the iteration).  part[kb][wg][c] = sum |t|^2 over the
+// workgroup's points; t is stored if tout != null.
+template <int NF, int B>
+__global__ __launch_bounds__(WG) void k_true_resid(
+    const double2* __restrict__ x, double2* __restrict__ tout, const double* __restrict__ vloc,
+    Coefs<double> co, int nx, int ny, int nz, const int32_t* __restrict__ prow,
+    const int32_t* __restrict__ patom, const double* __restrict__ pval,
+    const double2* __restrict__ dc, int n_atoms, const double2* __restrict__ zcol,
+    const int32_t* __restrict__ rhs, int R, int K, double* __restrict__ part) {
+  constexpr int PTS = WG / B;
+  const int tid = threadIdx.x, c = tid % B, ln = tid / B;
+  const int kb = blockIdx.y;
+  const int cb = kb / K;
+  const int nxy = nx * ny;
+  const int64_t N = (int64_t)nxy * nz;
+  const int64_t p = (int64_t)blockIdx.x * PTS + ln;
+  double acc = 0.0;
+  if (p < N) {
+    const double2* xb = x + (int64_t)kb * N * B + c;
+    const int ix = (int)(p % nx), iy = (int)((p / nx) % ny), iz = (int)(p / nxy);
+    const double2 xc = xb[p * B];
+    const double dg = co.c0 + vloc[p];
+    double hr = dg * xc.x, hi = dg * xc.y;
+    for (int k = 1; k <= NF; ++k) {
+      const int64_t xp = (int64_t)iz * nxy + iy * nx + wrapi(ix + k, nx);
+      const int64_t xm = (int64_t)iz * nxy + iy * nx + wrapi(ix - k, nx);
+      const int64_t yp = (int64_t)iz * nxy + wrapi(iy + k, ny) * nx + ix;
+      const int64_t ym = (int64_t)iz * nxy + wrapi(iy - k, ny) * nx + ix;
+      const double2 vxp = xb[xp * B], vxm = xb[xm * B], vyp = xb[yp * B], vym = xb[ym * B];
+      hr += co.cx[k] * (vxp.x + vxm.x) + co.cy[k] * (vyp.x + vym.x);
+      hi += co.cx[k] * (vxp.y + vxm.y) + co.cy[k] * (vyp.y + vym.y);
+      if (iz + k < nz) {
+        const double2 v = xb[(p + (int64_t)k * nxy) * B];
+        hr += co.cz[k] * v.x;
+        hi += co.cz[k] * v.y;
+      }
+      if (iz - k >= 0) {
+        const double2 v = xb[(p - (int64_t)k * nxy) * B];
+        hr += co.cz[k] * v.x;
+        hi += co.cz[k] * v.y;
+      }
+    }
+    if (prow) {
+      for (int e = prow[p]; e < prow[p + 1]; ++e) {
+        const double2* d = dc + ((int64_t)kb * n_atoms + patom[e]) * 4 * B + c;
+        for (int l = 0; l < 4; ++l) {
+          hr += pval[(int64_t)e * 4 + l] * d[l * B].x;
+          hi += pval[(int64_t)e * 4 + l] * d[l * B].y;
+        }
+      }
+    }
+    const double2 z = zcol[(int64_t)kb * B + c];
+    // t = b - z x + H x
+    double2 t = mk(hr - (z.x * xc.x - z.y * xc.y), hi - (z.x * xc.y + z.y * xc.x));
+    const int j = cb * B + c;
+    if (rhs && j < R && rhs[j] == p) t.x += 1.0;
+    if (tout) tout[(int64_t)kb * N * B + p * B + c] = t;
+    acc = t.x * t.x + t.y * t.y;
+  }
+  __shared__ double sh[WG];
+  sh[tid] = acc;
+  __syncthreads();
+  for (int s = PTS / 2; s >= 1; s >>= 1) {
+    if (ln < s) sh[tid] += sh[tid + s * B];
+    __syncthreads();
+  }
+  if (ln == 0) part[((int64_t)kb * gridDim.x + blockIdx.x) * B + c] = sh[tid];
+}
+
+// norm[kb*B + c] = sqrt(sum over the nwg partials), fixed order
+template <int B>
+__global__ __launch_bounds__(WG) void k_norms(const double* __restrict__ part, int nwg,
+                                               double* __restrict__ norm) {
+  constexpr int PTS = WG / B;
+  const int tid = threadIdx.x, c = tid % B, ln = tid / B, kb = blockIdx.x;
+  double acc = 0.0;
+  for (int w = ln; w < nwg; w += PTS) acc += part[((int64_t)kb * nwg + w) * B + c];
+  __shared__ double sh[WG];
+  sh[tid] = acc;
+  __syncthreads();
+  for (int s = PTS / 2; s >= 1; s >>= 1) {
+    if (ln < s) sh[tid] += sh[tid + s * B];
+    __syncthreads();
+  }
+  if (ln == 0) norm[(int64_t)kb * B + c] = sqrt(sh[tid]);
+}
+
+// ------------------------------------------------------------------ dense right-hand sides
+// r_{-1} = r_0 = b for dense right-hand sides (the refinement solves): column j
+// of block cb (j = cb*B + c) takes src[src_kb[j]][pnt][src_c[j]] * scale[j] from a
+// full-storage array of column width BS; padding planes and unused columns are
+// zero.  grid (ceil(bstride / WG), nb); partials of b^T b and ||b||^2 of the
+// stored (rounded) values per (block, workgroup, column).
+template <typename T, int B, int BS>
+__global__ __launch_bounds__(WG) void k_init_r_dense(
+    typename cplx_of<T>::type* r0, typename cplx_of<T>::type* r1, int64_t bstride, int64_t N,
+    int64_t pad, const double2* __restrict__ src, const int32_t* __restrict__ src_kb,
+    const int32_t* __restrict__ src_c, const double* __restrict__ scale, int R,
+    double2* __restrict__ prho, double* __restrict__ pnu) {
+  using cT = typename cplx_of<T>::type;
+  constexpr int PTS = WG / B;
+  const int tid = threadIdx.x, c = tid % B, ln = tid / B;
+  const int cb = blockIdx.y;
+  const int64_t w = (int64_t)blockIdx.x * WG + tid;
+  const int j = cb * B + c;
+  cT v{0, 0};
+  if (w < bstride) {
+    const int64_t pnt = w / B - pad;
+    if (j < R && pnt >= 0 && pnt < N) {
+      const double2 s = src[((int64_t)src_kb[j] * N + pnt) * BS + src_c[j]];
+      v = from_d<cT>(mk(s.x * scale[j], s.y * scale[j]));
+    }
+    r0[(int64_t)cb * bstride + w] = v;
+    r1[(int64_t)cb * bstride + w] = v;
+  }
+  const double2 vd = to_d(v);
+  __shared__ double2 s0[WG];
+  __shared__ double s1[WG];
+  s0[tid] = mk(vd.x * vd.x - vd.y * vd.y, 2.0 * vd.x * vd.y);
+  s1[tid] = vd.x * vd.x + vd.y * vd.y;
+  __syncthreads();
+  for (int s = PTS / 2; s >= 1; s >>= 1) {
+    if (ln < s) {
+      s0[tid] = cadd(s0[tid], s0[tid + s * B]);
+      s1[tid] += s1[tid + s * B];
+    }
+    __syncthreads();
+  }
+  if (ln == 0) {
+    const int64_t o = ((int64_t)cb * gridDim.x + blockIdx.x) * B + c;
+    prho[o] = s0[tid];
+    pnu[o] = s1[tid];
+  }
+}
+
+// rho_0 = b^T b and ||b|| of every column from the partials of k_init_r_dense
+template <int B>
+__global__ __launch_bounds__(WG) void k_dense_cols(const double2* __restrict__ prho,
+                                                    const double* __restrict__ pnu, int nwg,
+                                                    ColState* cols, int R) {
+  constexpr int PTS = WG / B;
+  const int tid = threadIdx.x, c = tid % B, ln = tid / B, cb = blockIdx.x;
+  double2 a = mk(0, 0);
+  double n = 0.0;
+  for (int w = ln; w < nwg; w += PTS) {
+    a = cadd(a, prho[((int64_t)cb * nwg + w) * B + c]);
+    n += pnu[((int64_t)cb * nwg + w) * B + c];
+  }
+  __shared__ double2 s0[WG];
+  __shared__ double s1[WG];
+  s0[tid] = a;
+  s1[tid] = n;
+  __syncthreads();
+  for (int s = PTS / 2; s >= 1; s >>= 1) {
+    if (ln < s) {
+      s0[tid] = cadd(s0[tid], s0[tid + s * B]);
+      s1[tid] += s1[tid + s * B];
+    }
+    __syncthreads();
+  }
+  if (ln == 0 && cb * B + c < R) {
+    ColState& cs = cols[cb * B + c];
+    cs.rho = s0[tid];
+    cs.bnorm = sqrt(s1[tid]);
+  }
+}
+
+// full storage with K = 1: x = 0, p = b (the plane-0 view of the padded r_0)
+template <typename T, int B>
+__global__ void k_init_xp_dense(double2* x, typename cplx_of<T>::type* p,
+                                const typename cplx_of<T>::type* __restrict__ r0p,
+                                int64_t bstride, int64_t N, int nb) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (int64_t)nb * N * B) return;
+  const int cb = (int)(gid / (N * B));
+  const int64_t w = gid % (N * B);
+  x[gid] = mk(0, 0);
+  p[gid] = r0p[(int64_t)cb * bstride + w];
+}
+
+// refinement update: x_out[src_kb[j]][pnt][src_c[j]] += back[j] * d[cb][pnt][c]
+// (d: full-storage K = 1 solution, j = cb*B + c)
+template <int B, int BS>
+__global__ void k_add_correction(double2* __restrict__ xout, const double2* __restrict__ d,
+                                 const int32_t* __restrict__ src_kb,
+                                 const int32_t* __restrict__ src_c,
+                                 const double* __restrict__ back, int R, int64_t N) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (int64_t)R * N) return;
+  const int j = (int)(gid / N);
+  const int64_t pnt = gid % N;
+  const int cb = j / B, c = j % B;
+  const double2 dv = d[((int64_t)cb * N + pnt) * B + c];
+  double2& xo = xout[((int64_t)src_kb[j] * N + pnt) * BS + src_c[j]];
+  xo = mk(xo.x + back[j] * dv.x, xo.y + back[j] * dv.y);
 }
 
 // G[k][j][i] = x[cb][k][i][c]  (j = cb*B + c), complex128 or complex64

@@ -13,10 +13,13 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <stdexcept>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "kernels.hpp"
@@ -79,6 +82,15 @@ void upload(DevBuf& b, const std::vector<U>& v, hipStream_t s) {
 
 unsigned nblocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
+// SCOCG_TRACE=1 prints per-pass refinement statistics to stderr
+bool trace_on() {
+  static const bool on = [] {
+    const char* e = getenv("SCOCG_TRACE");
+    return e && *e && *e != '0';
+  }();
+  return on;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------------------------
@@ -93,6 +105,8 @@ struct scocg_ctx {
   std::vector<double> coef;  // [3][nf+1]
   // operator arrays on the device (T = double or float by precision)
   DevBuf vloc, aptr, aidx, aval, aD, prow, patom, pval;
+  // FP64 copies for the true-residual pass (aliases of the above for SCOCG_FP64)
+  DevBuf vloc64, aval64, aD64, pval64;
   // last solve
   struct Solve {
     bool ok = false;
@@ -164,14 +178,51 @@ void upload_operator(scocg_ctx& h, const double* vloc, const int64_t* atom_ptr,
   upload(h.pval, pv, s);
 }
 
+// FP64 operator data for the true-residual pass of a complex64 handle
+void upload_operator64(scocg_ctx& h, const double* vloc, const int64_t* atom_ptr,
+                       const int64_t* atom_idx, const double* atom_P, const double* atom_D) {
+  hipStream_t s = h.stream;
+  upload(h.vloc64, std::vector<double>(vloc, vloc + h.N), s);
+  if (h.n_atoms == 0) return;
+  const int np = h.n_proj;
+  const int64_t E = atom_ptr[h.n_atoms];
+  std::vector<double> av(E * 4, 0.0), ad(h.n_atoms * 4, 0.0), pv(E * 4, 0.0);
+  std::vector<int32_t> pr(h.N + 1, 0);
+  for (int64_t e = 0; e < E; ++e)
+    for (int l = 0; l < np; ++l) av[e * 4 + l] = atom_P[e * np + l];
+  for (int a = 0; a < h.n_atoms; ++a)
+    for (int l = 0; l < np; ++l) ad[a * 4 + l] = atom_D[a * np + l];
+  for (int64_t e = 0; e < E; ++e) pr[atom_idx[e] + 1]++;
+  for (int64_t i = 0; i < h.N; ++i) pr[i + 1] += pr[i];
+  std::vector<int32_t> fill(pr.begin(), pr.end() - 1);
+  for (int a = 0; a < h.n_atoms; ++a)
+    for (int64_t e = atom_ptr[a]; e < atom_ptr[a + 1]; ++e) {
+      const int32_t slot = fill[atom_idx[e]]++;
+      for (int l = 0; l < 4; ++l) pv[(int64_t)slot * 4 + l] = av[e * 4 + l];
+    }
+  upload(h.aval64, av, s);
+  upload(h.aD64, ad, s);
+  upload(h.pval64, pv, s);
+}
+
 // ---------------------------------------------------------------------------------------------
 // Solver for one precision: T = vector/stencil arithmetic type, B = columns per block.
 template <typename T, int B>
 struct Solver {
   using cT = typename cplx_of<T>::type;
+  static constexpr int BW = B;
   scocg_ctx& h;
   scocg_ctx::Solve& S;
   explicit Solver(scocg_ctx& hh, scocg_ctx::Solve& ss) : h(hh), S(ss) {}
+
+  // operator arrays in the arithmetic type T: a complex64 handle keeps FP64 copies
+  // as well, which an FP64 solver on that handle (refinement escalation) uses
+  static constexpr bool DBL = std::is_same<T, double>::value;
+  bool use64() const { return DBL && h.precision != SCOCG_FP64; }
+  const T* op_vloc() const { return use64() ? h.vloc64.as<T>() : h.vloc.as<T>(); }
+  const T* op_aval() const { return use64() ? h.aval64.as<T>() : h.aval.as<T>(); }
+  const T* op_aD() const { return use64() ? h.aD64.as<T>() : h.aD.as<T>(); }
+  const T* op_pval() const { return use64() ? h.pval64.as<T>() : h.pval.as<T>(); }
 
   // Krylov vectors: per column block nz + 2*nf planes, nf zero planes on each side
   int64_t pad_points() const { return (int64_t)h.nf * h.nxy; }
@@ -251,7 +302,7 @@ struct Solver {
     }
     a.r = r;
     a.io = io;
-    a.vloc = h.vloc.as<T>();
+    a.vloc = op_vloc();
     a.co = make_coefs<T>(h);
     a.nx = h.nx; a.ny = h.ny; a.nz = h.nz; a.nxy = h.nxy;
     a.ntx = g.ntx; a.nty = g.nty;
@@ -260,7 +311,7 @@ struct Solver {
     a.nper = g.nper;
     a.prow = h.n_atoms ? h.prow.as<int32_t>() : nullptr;
     a.patom = h.patom.as<int32_t>();
-    a.pval = h.pval.as<T>();
+    a.pval = op_pval();
     a.dc = dc;
     a.n_atoms = h.n_atoms;
     a.cols = cols;
@@ -295,8 +346,8 @@ struct Solver {
     ProjArgs<T> pa{};
     pa.aptr = h.aptr.as<int32_t>();
     pa.aidx = h.aidx.as<int32_t>();
-    pa.aval = h.aval.as<T>();
-    pa.aD = h.aD.as<T>();
+    pa.aval = op_aval();
+    pa.aD = op_aD();
     pa.n_proj = h.n_proj;
     pa.n_atoms = h.n_atoms;
     pa.dc = dc;
@@ -372,8 +423,75 @@ struct Solver {
     mark(ev, SCOCG_K_SHIFT, 1);
   }
 
-  int run(int K, const double* z, int R, const int64_t* rhs_idx, int nS_in, const int64_t* s_idx,
-          const scocg_solve_opts& o, scocg_report* rep) {
+  // FP64 operator data (the handle's own arrays for SCOCG_FP64, the FP64 copies otherwise)
+  const double* vloc64() const {
+    return h.precision == SCOCG_FP64 ? h.vloc.as<double>() : h.vloc64.as<double>();
+  }
+  ProjArgs<double> proj64(double2* dc) const {
+    const bool f = h.precision == SCOCG_FP64;
+    ProjArgs<double> pa{};
+    pa.aptr = h.aptr.as<int32_t>();
+    pa.aidx = h.aidx.as<int32_t>();
+    pa.aval = f ? h.aval.as<double>() : h.aval64.as<double>();
+    pa.aD = f ? h.aD.as<double>() : h.aD64.as<double>();
+    pa.n_proj = h.n_proj;
+    pa.n_atoms = h.n_atoms;
+    pa.dc = dc;
+    pa.qa = nullptr;
+    return pa;
+  }
+
+  // FP64 ||e_j - (z_k - H) x^(k)_j|| for every pair of a full-storage solve
+  // (x in [nb*K][N][B]); t is kept in `tbuf` when it is non-null.  Returns the
+  // norms as [nb*K*B] (block kb = cb*K + k, column c).
+  std::vector<double> true_residuals(DevBuf* tbuf) {
+    const int nblk = S.nb * S.K;
+    const int64_t N = h.N;
+    constexpr int PTS = WG / B;
+    const int gx = (int)nblocks(N, PTS);
+    DevBuf part, norms, dc64;
+    part.alloc((size_t)nblk * gx * B * sizeof(double));
+    norms.alloc((size_t)nblk * B * sizeof(double));
+    if (h.n_atoms) {
+      dc64.alloc((size_t)nblk * h.n_atoms * 4 * B * sizeof(double2));
+      hipLaunchKernelGGL((k_proj<double, B>), dim3(h.n_atoms, nblk), dim3(WG), 0, h.stream,
+                         S.x.as<double2>(), N * B, proj64(dc64.as<double2>()), nullptr);
+      KCHK();
+    }
+    if (tbuf) tbuf->alloc((size_t)nblk * N * B * sizeof(double2));
+    const Coefs<double> co = make_coefs<double>(h);
+    const dim3 g(gx, nblk);
+    const double2* x = S.x.as<double2>();
+    double2* t = tbuf ? tbuf->as<double2>() : nullptr;
+    const int32_t* prow = h.n_atoms ? h.prow.as<int32_t>() : nullptr;
+    const double* pv = h.n_atoms ? (h.precision == SCOCG_FP64 ? h.pval.as<double>()
+                                                               : h.pval64.as<double>())
+                                 : nullptr;
+#define SCOCG_TR(NFV)                                                                         \
+  hipLaunchKernelGGL((k_true_resid<NFV, B>), g, dim3(WG), 0, h.stream, x, t, vloc64(), co, h.nx, \
+                     h.ny, h.nz, prow, h.patom.as<int32_t>(), pv, dc64.as<double2>(),          \
+                     h.n_atoms, S.z.as<double2>(), S.rhs.as<int32_t>(), S.R, S.K,              \
+                     part.as<double>())
+    switch (h.nf) {
+      case 1: SCOCG_TR(1); break;
+      case 2: SCOCG_TR(2); break;
+      case 3: SCOCG_TR(3); break;
+      default: SCOCG_TR(4); break;
+    }
+#undef SCOCG_TR
+    KCHK();
+    hipLaunchKernelGGL((k_norms<B>), dim3(nblk), dim3(WG), 0, h.stream, part.as<double>(), gx,
+                       norms.as<double>());
+    KCHK();
+    std::vector<double> out((size_t)nblk * B);
+    HIPCHK(hipMemcpyAsync(out.data(), norms.p, out.size() * sizeof(double), hipMemcpyDeviceToHost,
+                          h.stream));
+    HIPCHK(hipStreamSynchronize(h.stream));
+    return out;
+  }
+
+  // ---- solve state
+  void alloc_state(int K, int R, bool full, int nS, const scocg_solve_opts& o) {
     require((R + B - 1) / B <= 65536, "too many column blocks");
     require(control_lds(K) <= 128 * 1024, "too many energies for one column block (K*B)");
     HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_control<B>),
@@ -383,24 +501,9 @@ struct Solver {
     S.K = K;
     S.R = R;
     S.nb = (R + B - 1) / B;
-    S.full = o.full != 0;
-    S.nS = S.full ? (int)h.N : (s_idx ? nS_in : R);
+    S.full = full;
+    S.nS = nS;
     const int nb = S.nb;
-    hipStream_t st = h.stream;
-    // inputs
-    std::vector<double2> zh(K);
-    for (int k = 0; k < K; ++k) zh[k] = mk(z[2 * k], z[2 * k + 1]);
-    std::vector<int32_t> rh(R);
-    for (int j = 0; j < R; ++j) rh[j] = (int32_t)rhs_idx[j];
-    upload(S.rhs, rh, st);
-    if (!S.full) {
-      std::vector<int32_t> sr(S.nS);
-      for (int i = 0; i < S.nS; ++i) sr[i] = (int32_t)(s_idx ? s_idx[i] : rhs_idx[i]);
-      upload(S.srow, sr, st);
-    }
-    DevBuf zk;
-    upload(zk, zh, st);
-    // state
     S.g = plan(nb, o.tile, o.zchunk);
     S.nwg = S.g.nwg;
     const size_t vec = (size_t)nb * bstride() * sizeof(cT);
@@ -424,27 +527,64 @@ struct Solver {
     S.part0.alloc((size_t)nb * S.nwg * B * sizeof(double2));
     S.part1.alloc((size_t)nb * S.nwg * B * sizeof(double));
     if (!S.h_flags) HIPCHK(hipHostMalloc((void**)&S.h_flags, sizeof(int32_t) * 65536));
+  }
 
-    hipEvent_t e0, e1;
-    HIPCHK(hipEventCreate(&e0));
-    HIPCHK(hipEventCreate(&e1));
-    HIPCHK(hipEventRecord(e0, st));
-    const int seed0 = o.init_seed < 0 ? K / 2 : o.init_seed;
+  // unit right-hand sides e_{rhs[j]}, energies zk[K] shared by every column
+  void init_unit(const double2* zk, int seed0) {
+    hipStream_t st = h.stream;
+    const int nb = S.nb, K = S.K, R = S.R;
+    const size_t nkb = (size_t)nb * K * B;
     hipLaunchKernelGGL((k_init_r<T, B>), dim3(nblocks((int64_t)nb * bstride(), WG)), dim3(WG), 0,
                        st, S.r0.as<cT>(), S.r1.as<cT>(), bstride(), h.N, pad_points(),
                        S.rhs.as<int32_t>(), R, nb);
     KCHK();
-    hipLaunchKernelGGL((k_init_xp<T, B>), dim3(nblocks((int64_t)xp, WG)), dim3(WG), 0, st,
+    hipLaunchKernelGGL((k_init_xp<T, B>), dim3(nblocks((int64_t)nkb * S.nS, WG)), dim3(WG), 0, st,
                        S.x.as<double2>(), S.p.as<cT>(), S.full ? nullptr : S.srow.as<int32_t>(),
                        S.nS, K, nb, S.rhs.as<int32_t>(), R);
     KCHK();
     hipLaunchKernelGGL((k_init_state<B>), dim3(nblocks((int64_t)nkb, WG)), dim3(WG), 0, st,
                        S.cols.as<ColState>(), S.sh.as<ShiftState>(), S.coef.as<ShiftCoef>(),
-                       S.z.as<double2>(), zk.as<double2>(), K, nb, R, seed0, S.list.as<int32_t>(),
+                       S.z.as<double2>(), zk, nullptr, K, nb, R, seed0, S.list.as<int32_t>(),
                        S.cnt.as<int32_t>(), S.k5cnt.as<int32_t>(), S.blk_active.as<int32_t>(),
                        S.blk_iter.as<int32_t>());
     KCHK();
+  }
 
+  // dense right-hand sides (K = 1, full storage): column j solves
+  // (zpc[j] - H) d = scale[j] * src[src_kb[j]][:][src_c[j]]
+  template <int BS>
+  void init_dense(const double2* zpc, const double2* src, const int32_t* src_kb,
+                  const int32_t* src_c, const double* scale) {
+    hipStream_t st = h.stream;
+    const int nb = S.nb, R = S.R;
+    const int gx = (int)nblocks(bstride(), WG);
+    DevBuf prho, pnu;
+    prho.alloc((size_t)nb * gx * B * sizeof(double2));
+    pnu.alloc((size_t)nb * gx * B * sizeof(double));
+    hipLaunchKernelGGL((k_init_r_dense<T, B, BS>), dim3(gx, nb), dim3(WG), 0, st, S.r0.as<cT>(),
+                       S.r1.as<cT>(), bstride(), h.N, pad_points(), src, src_kb, src_c, scale, R,
+                       prho.as<double2>(), pnu.as<double>());
+    KCHK();
+    hipLaunchKernelGGL((k_init_xp_dense<T, B>), dim3(nblocks((int64_t)nb * h.N * B, WG)), dim3(WG),
+                       0, st, S.x.as<double2>(), S.p.as<cT>(), plane0(S.r0.as<cT>()), bstride(),
+                       h.N, nb);
+    KCHK();
+    hipLaunchKernelGGL((k_init_state<B>), dim3(nblocks((int64_t)nb * B, WG)), dim3(WG), 0, st,
+                       S.cols.as<ColState>(), S.sh.as<ShiftState>(), S.coef.as<ShiftCoef>(),
+                       S.z.as<double2>(), zpc, zpc, 1, nb, R, 0, S.list.as<int32_t>(),
+                       S.cnt.as<int32_t>(), S.k5cnt.as<int32_t>(), S.blk_active.as<int32_t>(),
+                       S.blk_iter.as<int32_t>());
+    KCHK();
+    hipLaunchKernelGGL((k_dense_cols<B>), dim3(nb), dim3(WG), 0, st, prho.as<double2>(),
+                       pnu.as<double>(), gx, S.cols.as<ColState>(), R);
+    KCHK();
+    HIPCHK(hipStreamSynchronize(st));  // prho, pnu are freed on return
+  }
+
+  // the seed iterations, polling the block flags every `poll` iterations
+  int64_t iterate(const scocg_solve_opts& o, double* kms, int64_t* kcount) {
+    hipStream_t st = h.stream;
+    const int nb = S.nb;
     int poll = o.poll_every > 0 ? o.poll_every : 16;
     if (poll & 1) ++poll;  // even: the buffer and list parities return to 0 after each poll
     int64_t it = 0;
@@ -456,8 +596,6 @@ struct Solver {
       evs.resize((size_t)poll * 2 * SCOCG_K_FAMILIES);
       for (auto& e : evs) HIPCHK(hipEventCreate(&e));
     }
-    double kms[SCOCG_K_FAMILIES] = {0};
-    int64_t kcount[SCOCG_K_FAMILIES] = {0};
     auto ev_of = [&](int s2) { return o.timing ? &evs[(size_t)s2 * 2 * SCOCG_K_FAMILIES] : nullptr; };
     // events cannot be read back from captured graph nodes: timing runs use direct launches
     const bool use_graph = o.use_graph && !o.timing;
@@ -493,14 +631,176 @@ struct Solver {
       if (!any || it >= o.max_iter + poll) break;
     }
     for (auto& e : evs) (void)hipEventDestroy(e);
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    return it;
+  }
+
+  void release_workspace() {
+    S.r0.release();
+    S.r1.release();
+    S.part0.release();
+    S.part1.release();
+    S.dc.release();
+    S.qa.release();
+  }
+
+  // One correction pass with an inner solver of type SolverIn: every pair whose
+  // FP64 true residual misses tol gets a single-energy COCG solve of
+  // (z_k - H) d = t / ||t|| (at most `cap` iterations) and x += ||t|| d in FP64.
+  // Returns the number of pairs corrected; tres (in/out) holds the true
+  // residuals ([nb*K*B] layout).
+  template <typename SolverIn>
+  int64_t correction_pass(const scocg_solve_opts& o, int pass, int64_t cap, const double2* zk_host,
+                          std::vector<double>& tres) {
+    constexpr int BI = SolverIn::BW;
+    std::vector<int32_t> kb, cc;
+    std::vector<double> sc, back;
+    std::vector<double2> zp;
+    double tmax = 0.0;
+    for (int cb = 0; cb < S.nb; ++cb)
+      for (int k = 0; k < S.K; ++k)
+        for (int c = 0; c < B; ++c) {
+          const double t = tres[((size_t)cb * S.K + k) * B + c];
+          if (cb * B + c >= S.R || !(t > o.tol)) continue;
+          kb.push_back(cb * S.K + k);
+          cc.push_back(c);
+          sc.push_back(1.0 / t);
+          back.push_back(t);
+          zp.push_back(zk_host[k]);
+          tmax = std::max(tmax, t);
+        }
+    if (kb.empty()) return 0;
+    const int Rin = (int)kb.size();
+    DevBuf d_kb, d_c, d_sc, d_back, d_z, tbuf;
+    tres = true_residuals(&tbuf);  // the residual vectors themselves
+    upload(d_kb, kb, h.stream);
+    upload(d_c, cc, h.stream);
+    upload(d_sc, sc, h.stream);
+    upload(d_back, back, h.stream);
+    // per-column energies of the inner solve, padded to whole blocks
+    zp.resize((size_t)((Rin + BI - 1) / BI) * BI, zp.back());
+    upload(d_z, zp, h.stream);
+    scocg_ctx::Solve Sin;
+    SolverIn in(h, Sin);
+    scocg_solve_opts oi = o;
+    oi.full = 1;
+    oi.init_seed = 0;
+    oi.tile = 0;
+    oi.max_iter = cap;
+    // the corrected residual is ||t|| times the inner relative residual
+    oi.tol = std::min(0.5, std::max(1e-12, 0.25 * o.tol / tmax));
+    oi.timing = 0;
+    in.alloc_state(1, Rin, true, (int)h.N, oi);
+    in.template init_dense<B>(d_z.as<double2>(), tbuf.as<double2>(), d_kb.as<int32_t>(),
+                              d_c.as<int32_t>(), d_sc.as<double>());
+    double km[SCOCG_K_FAMILIES] = {0};
+    int64_t kc[SCOCG_K_FAMILIES] = {0};
+    const int64_t it_in = in.iterate(oi, km, kc);
+    if (trace_on()) {
+      std::vector<ShiftState> si((size_t)Sin.nb * BI);
+      HIPCHK(hipMemcpy(si.data(), Sin.sh.p, si.size() * sizeof(ShiftState), hipMemcpyDeviceToHost));
+      int conv = 0, brk = 0;
+      double emax = 0;
+      for (int j = 0; j < Rin; ++j) {
+        conv += si[j].status == ST_CONVERGED && !si[j].active;
+        brk += si[j].status == ST_BREAKDOWN;
+        emax = std::max(emax, si[j].est);
+      }
+      fprintf(stderr,
+              "[scocg] correction pass %d (%s inner): %d pairs, max true residual %.3e, inner "
+              "tol %.3e, %lld inner iterations, %d converged, %d breakdown, max est %.3e\n",
+              pass, BI == 8 ? "complex128" : "complex64", Rin, tmax, oi.tol, (long long)it_in,
+              conv, brk, emax);
+    }
+    hipLaunchKernelGGL((k_add_correction<BI, B>), dim3(nblocks((int64_t)Rin * h.N, WG)), dim3(WG),
+                       0, h.stream, S.x.as<double2>(), Sin.x.as<double2>(), d_kb.as<int32_t>(),
+                       d_c.as<int32_t>(), d_back.as<double>(), Rin, h.N);
+    KCHK();
+    tbuf.release();
+    tres = true_residuals(nullptr);
+    return Rin;
+  }
+
+  // Refinement of a full-storage complex64 solve: up to `passes` correction
+  // passes with complex64 inner solves (each capped at twice the outer seed
+  // iterations, since plain FP32 COCG can stall on the hardest energies), then
+  // one pass with complex128 inner solves for the pairs still above tol.
+  int64_t refine(const scocg_solve_opts& o, int passes, int64_t outer_iters,
+                 const double2* zk_host, std::vector<double>& tres) {
+    int64_t refined = 0;
+    const int64_t cap = std::max<int64_t>(2 * outer_iters, 200);
+    auto worst = [&]() {
+      double m = 0.0;
+      for (int cb = 0; cb < S.nb; ++cb)
+        for (int k = 0; k < S.K; ++k)
+          for (int c = 0; c < B && cb * B + c < S.R; ++c)
+            m = std::max(m, tres[((size_t)cb * S.K + k) * B + c]);
+      return m;
+    };
+    for (int pass = 0; pass < passes; ++pass) {
+      const double before = worst();
+      const int64_t n = correction_pass<Solver<T, B>>(o, pass, cap, zk_host, tres);
+      refined += n;
+      // stop the complex64 passes once they stall (worst residual not cut 10x)
+      if (!n || worst() > 0.1 * before) break;
+    }
+    if constexpr (!DBL) refined += correction_pass<Solver<double, 8>>(o, passes, 4 * cap, zk_host, tres);
+    return refined;
+  }
+
+  int run(int K, const double* z, int R, const int64_t* rhs_idx, int nS_in, const int64_t* s_idx,
+          const scocg_solve_opts& o, scocg_report* rep) {
+    const bool full = o.full != 0;
+    const int nS = full ? (int)h.N : (s_idx ? nS_in : R);
+    hipStream_t st = h.stream;
+    // inputs
+    std::vector<double2> zh(K);
+    for (int k = 0; k < K; ++k) zh[k] = mk(z[2 * k], z[2 * k + 1]);
+    std::vector<int32_t> rh(R);
+    for (int j = 0; j < R; ++j) rh[j] = (int32_t)rhs_idx[j];
+    upload(S.rhs, rh, st);
+    if (!full) {
+      std::vector<int32_t> sr(nS);
+      for (int i = 0; i < nS; ++i) sr[i] = (int32_t)(s_idx ? s_idx[i] : rhs_idx[i]);
+      upload(S.srow, sr, st);
+    }
+    DevBuf zk;
+    upload(zk, zh, st);
+    alloc_state(K, R, full, nS, o);
+    const int nb = S.nb;
+    const size_t nkb = (size_t)nb * K * B;
+
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    HIPCHK(hipEventRecord(e0, st));
+    init_unit(zk.as<double2>(), o.init_seed < 0 ? K / 2 : o.init_seed);
+    double kms[SCOCG_K_FAMILIES] = {0};
+    int64_t kcount[SCOCG_K_FAMILIES] = {0};
+    iterate(o, kms, kcount);
+    release_workspace();
+
+    // FP64 true residuals of every pair (full storage only); refinement passes for
+    // complex64 solves.  Both are inside the timed region.
+    std::vector<double> tres;
+    int64_t refined = 0;
+    if (S.full && o.refine >= 0) {
+      tres = true_residuals(nullptr);
+      if (h.precision == SCOCG_MIXED && o.refine > 0) {
+        int32_t mx = 0;
+        std::vector<ColState> c0((size_t)nb * B);
+        HIPCHK(hipMemcpy(c0.data(), S.cols.p, c0.size() * sizeof(ColState), hipMemcpyDeviceToHost));
+        for (int j = 0; j < R; ++j) mx = std::max(mx, c0[j].iters);
+        refined = refine(o, o.refine, mx, zh.data(), tres);
+      }
+    }
     HIPCHK(hipEventRecord(e1, st));
     HIPCHK(hipEventSynchronize(e1));
     float ms = 0.f;
     HIPCHK(hipEventElapsedTime(&ms, e0, e1));
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    if (gexec) (void)hipGraphExecDestroy(gexec);
-    if (graph) (void)hipGraphDestroy(graph);
 
     // report
     std::vector<ShiftState> shh(nkb);
@@ -517,7 +817,8 @@ struct Solver {
     }
     for (int k = 0; k < K; ++k)
       for (int j = 0; j < R; ++j) {
-        const ShiftState& ss = shh[((size_t)(j / B) * K + k) * B + (j % B)];
+        const size_t so = ((size_t)(j / B) * K + k) * B + (j % B);
+        const ShiftState& ss = shh[so];
         int stt = ss.status;
         if (ss.active) stt = ST_MAXITER;
         if (stt == ST_MAXITER && rc == SCOCG_OK) rc = SCOCG_NOT_ALL_CONVERGED;
@@ -526,14 +827,14 @@ struct Solver {
         if (rep) {
           if (rep->iters) rep->iters[o2] = ss.iters;
           if (rep->est_resid) rep->est_resid[o2] = ss.est;
-          if (rep->true_resid) rep->true_resid[o2] = NAN;
+          if (rep->true_resid) rep->true_resid[o2] = tres.empty() ? NAN : tres[so];
           if (rep->status) rep->status[o2] = stt;
         }
       }
     if (rep) {
       rep->seed_iters = seed_iters;
       rep->n_switches = nsw;
-      rep->refined = 0;
+      rep->refined = refined;
       rep->solve_ms = ms;
       rep->block_iters = 0;
       for (int b = 0; b < nb; ++b) rep->block_iters += bit[b];
@@ -544,13 +845,6 @@ struct Solver {
         rep->kernel_launches[f] = kcount[f];
       }
     }
-    // release the Krylov workspace; x stays for scocg_green_columns
-    S.r0.release();
-    S.r1.release();
-    S.part0.release();
-    S.part1.release();
-    S.dc.release();
-    S.qa.release();
     S.ok = true;
     return rc;
   }
@@ -659,10 +953,12 @@ int scocg_create(const scocg_grid* g, const double* coef, const double* vloc, in
       require(all_finite(atom_D, (int64_t)n_atoms * g->n_proj), "non-finite projector energy");
     }
     h->n_atoms = n_atoms;
-    if (precision == SCOCG_FP64)
+    if (precision == SCOCG_FP64) {
       upload_operator<double>(*h, vloc, atom_ptr, atom_idx, atom_P, atom_D);
-    else
+    } else {
       upload_operator<float>(*h, vloc, atom_ptr, atom_idx, atom_P, atom_D);
+      upload_operator64(*h, vloc, atom_ptr, atom_idx, atom_P, atom_D);
+    }
     *out = h.release();
     return SCOCG_OK;
   });
