@@ -7,7 +7,9 @@ enqueues the solve and copies G_S into a device buffer.
 
 Prints one JSON line.  Besides the contract fields it carries
   roofline:     the dominant kernel (the r_{n+1} stencil/update pass), algorithmic
-                bytes per launch / its average HIP-event duration in the timed steps,
+                bytes per launch / its average HIP-event duration in the timed steps
+                (the timed steps bracket only that kernel with events: direct launches,
+                two event records per iteration),
   cpu_baseline: the CPU FP64 oracle (conventional COCG per pair) on a bounded
                 sample of the same workload, timed on this host.
 """
@@ -38,40 +40,77 @@ def parse():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-graph", action="store_true")
-    ap.add_argument("--cpu-pairs", type=int, default=16)
+    ap.add_argument("--cpu-energies", type=int, default=8)
+    ap.add_argument("--cpu-cols", type=int, default=8)
+    ap.add_argument("--cpu-iters", type=int, default=128)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--max-iter", type=int, default=0,
+                    help="cap the seed iterations (short counter-collection runs only)")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="before the solves, one plain device-to-device copy of this many "
+                         "MiB whose counter readings scale the HBM byte counters")
+    ap.add_argument("--no-diag", action="store_true",
+                    help="skip the untimed per-family timing solve")
     return ap.parse_args()
 
 
-def cpu_baseline(p, n_pairs, tol):
-    """Oracle (plain C, one pair per host thread) on a fixed sample of (energy, column)
-    pairs spread over the energy window."""
-    from concurrent.futures import ThreadPoolExecutor
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stencil_update_medium_fp64.txt")
+KERNEL_SOURCES = ("paper_1502_00081_amd/csrc/kernels.hpp", "paper_1502_00081_amd/csrc/scocg.hip")
 
+
+def kernel_source_hash():
+    import hashlib
+    d = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            d.update(fh.read())
+    return d.hexdigest()[:16]
+
+
+def measured_traffic(workload, precision):
+    """HBM bytes per launch of the r_{n+1} pass from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's readings); None when the
+    summary is missing, covers another workload, or the kernels changed since."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            kv = dict(l.split(":", 1) for l in fh if ":" in l and not l.startswith("#"))
+    except OSError:
+        return None, None
+    kv = {k.strip(): v.strip() for k, v in kv.items()}
+    if (kv.get("workload") != workload or kv.get("precision") != precision
+            or kv.get("kernel_source_sha256_16") != kernel_source_hash()):
+        return None, None
+    return float(kv["traffic_bytes_per_launch"]), float(kv["algorithmic_bytes_per_launch"])
+
+
+def cpu_baseline(p, n_energies, n_cols, iters_cap, tol, mean_iters):
+    """Oracle (plain C, OpenMP over pairs) on a bounded sample: n_energies energies
+    evenly spread over the window x n_cols seeded columns, each pair run for at most
+    iters_cap conventional COCG iterations.  The measured pair-iterations per second are
+    converted to converged solves/s with the workload's mean iterations per converged
+    pair (the per-pair counts of the GPU solve: shifted and conventional COCG take the
+    same iterations in exact arithmetic, and the parity tests bound the gap)."""
     import oracle
     K, R = p.z.size, p.rhs_idx.size
     rng = np.random.default_rng(2024)
-    ks = np.linspace(0, K - 1, n_pairs).round().astype(int)
-    js = rng.choice(R, n_pairs, replace=n_pairs > R)
-    pairs = list(zip(ks.tolist(), js.tolist()))
-    threads = min(n_pairs, int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
-
-    def one(kj):
-        _, it, st, _ = oracle.cocg_unit_columns(p, p.z, p.rhs_idx, p.rhs_idx, [kj], tol=tol)
-        say(f"cpu baseline pair {kj}: {int(it[0])} iterations")
-        return int(it[0]), int(st[0])
-
+    ks = np.linspace(0, K - 1, n_energies).round().astype(int)
+    js = rng.choice(R, n_cols, replace=n_cols > R)
+    pairs = [(int(k), int(j)) for k in ks for j in js]
+    threads = min(len(pairs), int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
     t0 = time.perf_counter()
-    with ThreadPoolExecutor(max_workers=threads) as ex:
-        res = list(ex.map(one, pairs))
+    _, it, st, _ = oracle.cocg_unit_columns(p, p.z, p.rhs_idx, p.rhs_idx, pairs, tol=tol,
+                                            max_iter=iters_cap)
     dt = time.perf_counter() - t0
-    conv = sum(1 for _, s in res if s == oracle.CONVERGED)
-    mean_it = float(np.mean([i for i, _ in res]))
-    return {"value": conv / dt, "unit": "solves/s", "cores": threads, "kind": "oracle",
-            "sample": f"{n_pairs} (energy, column) pairs of the same workload (energies evenly "
-                      f"spread over the window, columns seeded), conventional FP64 COCG per "
-                      f"pair to {tol:g}, one pair per thread; {dt:.1f} s wall, mean "
-                      f"{mean_it:.0f} iterations per pair"}
+    done = int(it.sum())
+    rate = done / dt
+    return {"value": rate / mean_iters, "unit": "solves/s", "cores": threads, "kind": "oracle",
+            "sample": f"{len(pairs)} (energy, column) pairs of the same workload ({n_energies} "
+                      f"energies evenly spread over the window x {n_cols} seeded columns), "
+                      f"conventional FP64 COCG per pair, OpenMP over pairs, each capped at "
+                      f"{iters_cap} iterations: {done} pair-iterations in {dt:.1f} s wall = "
+                      f"{rate:.1f} pair-iterations/s, divided by the workload's mean of "
+                      f"{mean_iters:.0f} iterations per converged pair (from the GPU solve's "
+                      f"per-pair counts)"}
 
 
 def main():
@@ -90,7 +129,18 @@ def main():
     h = scocg.create_from_problem(p, precision=prec, stream=stream)
     K, R = p.z.size, p.rhs_idx.size
     out = torch.empty((K, R, R), dtype=torch.complex128, device="cuda")
-    kw = dict(tol=a.tol, timing=True)
+    kw = dict(tol=a.tol, timing=2)
+    if a.max_iter > 0:
+        kw["max_iter"] = a.max_iter
+    if a.calibrate_copy_mib > 0:
+        nbytes = a.calibrate_copy_mib << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        say(f"calibration copy: {nbytes} bytes read, {nbytes} bytes written")
+        del src, dst
     say(f"workload {p.name}: N={p.n}, K={K}, R={R}, precision {a.precision}")
     for i in range(a.warmup):
         rc, rep = h.solve(p.z, p.rhs_idx, **kw)
@@ -115,7 +165,7 @@ def main():
     upd_ms = sum(r["kernel_ms"]["update"] for r in reps)
     upd_launches = sum(r["kernel_launches"]["update"] for r in reps)
     achieved = upd_bytes / (upd_ms * 1e-3) / 1e9
-    total_ms = {k: sum(r["kernel_ms"][k] for r in reps) for k in scocg.KERNEL_FAMILIES}
+    traffic, traffic_alg = measured_traffic(p.name, a.precision)
     line = {
         "metric": "converged (shift x column) solves/s at 1e-8 rel residual",
         "value": converged / dt,
@@ -134,26 +184,39 @@ def main():
                    "eta": float(p.z.imag[0]), "tol": a.tol, "precision": a.precision},
         "roofline": {"bound": "hbm", "kernel": "k_stencil<UPDATE>", "achieved": achieved,
                      "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
-                     "traffic": None,
+                     "traffic": traffic,
                      "avg_launch_us": upd_ms * 1e3 / max(upd_launches, 1),
-                     "bytes_per_launch": upd_bytes / max(upd_launches, 1)},
+                     "bytes_per_launch": upd_bytes / max(upd_launches, 1),
+                     "traffic_note": None if traffic is None else
+                     f"HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated) over "
+                     f"launches whose algorithmic bytes are {traffic_alg:.4g}: ratio "
+                     f"{traffic / traffic_alg:.3f}"},
         "seed_iters": int(reps[-1]["seed_iters"]),
-        "kernel_ms_per_step": {k: v / a.steps for k, v in total_ms.items()},
         "solve_ms_device": float(np.mean([r["solve_ms"] for r in reps])),
     }
-    # the same solve replayed as captured hipGraphs (per-kernel events cannot be read
-    # back from graph nodes, so the timed steps above use direct launches)
+    # untimed diagnostics: per-family kernel time from a solve with every launch
+    # bracketed by events, and the same solve replayed as captured hipGraphs (events
+    # cannot be read back from graph nodes, so the timed steps use direct launches)
+    if not a.no_diag:
+        rc, rep = h.solve(p.z, p.rhs_idx, **dict(kw, timing=1))
+        line["kernel_ms_per_step"] = {k: rep["kernel_ms"][k] for k in scocg.KERNEL_FAMILIES
+                                      if rep["kernel_launches"][k]}
+        say(f"per-family kernel ms: {line['kernel_ms_per_step']}")
     if not a.no_graph:
         torch.cuda.synchronize()
         tg = time.perf_counter()
-        h.solve(p.z, p.rhs_idx, tol=a.tol, use_graph=True)
+        h.solve(p.z, p.rhs_idx, **dict(kw, timing=0, use_graph=True))
         h.green_columns(out)
         torch.cuda.synchronize()
         line["ms_per_step_graph_replay"] = (time.perf_counter() - tg) * 1e3
     h.destroy()
     if not a.no_cpu_baseline:
-        say(f"cpu baseline: oracle on {a.cpu_pairs} pairs")
-        line["cpu_baseline"] = cpu_baseline(p, a.cpu_pairs, a.tol)
+        say(f"cpu baseline: oracle on {a.cpu_energies}x{a.cpu_cols} pairs, "
+            f"{a.cpu_iters} iterations each")
+        conv = reps[-1]["status"] == scocg.PAIR_CONVERGED
+        mean_iters = float(reps[-1]["iters"][conv].mean()) if conv.any() else float("nan")
+        line["cpu_baseline"] = cpu_baseline(p, a.cpu_energies, a.cpu_cols, a.cpu_iters, a.tol,
+                                            mean_iters)
     print(json.dumps(line), flush=True)
 
 

@@ -105,7 +105,8 @@ typedef struct {
     int32_t use_graph;   /* 1: replay the per-poll iterations as one captured hipGraph */
     int32_t timing;      /* 1: bracket every kernel launch with HIP events and report the
                             summed durations per kernel family (scocg_report.kernel_ms);
-                            launches are then direct (use_graph is ignored) */
+                            2: only the r_{n+1} pass (SCOCG_K_UPDATE), the lightest probe.
+                            Launches are then direct (use_graph is ignored) */
     int32_t tile;        /* stencil workgroup shape, x-y tile TX x TY and threads per group
                             (0 -> 1 for SCOCG_FP64, 3 for SCOCG_MIXED). SCOCG_FP64: 1 = 16x8/1024, 2 = 16x4/512,
                             3 = 8x8/512, 4 = 16x8/512.  SCOCG_MIXED: 1 = 16x8/1024,
@@ -135,8 +136,8 @@ typedef struct {
                             per block: 8 for SCOCG_FP64, 16 for SCOCG_MIXED) */
     int32_t block_width; /* out: B */
     int32_t n_blocks;    /* out: column blocks */
-    double kernel_ms[SCOCG_K_FAMILIES];      /* out (timing = 1): summed launch durations */
-    int64_t kernel_launches[SCOCG_K_FAMILIES]; /* out (timing = 1): launches timed */
+    double kernel_ms[SCOCG_K_FAMILIES];      /* out (timing != 0): summed launch durations */
+    int64_t kernel_launches[SCOCG_K_FAMILIES]; /* out (timing != 0): launches timed */
 } scocg_report;
 
 /*

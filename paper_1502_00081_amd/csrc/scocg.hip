@@ -367,8 +367,11 @@ struct Solver {
   static size_t control_lds(int K) { return (size_t)K * B * (sizeof(double) + 1); }
 
   // ev: null, or 2*SCOCG_K_FAMILIES events recorded around the launches of this iteration
+  // timing mode 1 records every family, mode 2 only the r_{n+1} pass
+  int timing_mode = 0;
   void mark(hipEvent_t* ev, int fam, int end) {
-    if (ev) HIPCHK(hipEventRecord(ev[2 * fam + end], h.stream));
+    if (!ev || (timing_mode == 2 && fam != SCOCG_K_UPDATE)) return;
+    HIPCHK(hipEventRecord(ev[2 * fam + end], h.stream));
   }
 
   void one_iteration(int cur, int par, const scocg_solve_opts& o, hipEvent_t* ev) {
@@ -591,13 +594,15 @@ struct Solver {
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
     // timing: one event pair per kernel family per iteration of a poll chunk
+    timing_mode = o.timing;
     std::vector<hipEvent_t> evs;
     if (o.timing) {
       evs.resize((size_t)poll * 2 * SCOCG_K_FAMILIES);
       for (auto& e : evs) HIPCHK(hipEventCreate(&e));
     }
     auto ev_of = [&](int s2) { return o.timing ? &evs[(size_t)s2 * 2 * SCOCG_K_FAMILIES] : nullptr; };
-    // events cannot be read back from captured graph nodes: timing runs use direct launches
+    // events recorded during capture cannot be read back after a replay on this
+    // runtime: timing runs use direct launches
     const bool use_graph = o.use_graph && !o.timing;
     while (true) {
       if (use_graph) {
@@ -619,6 +624,7 @@ struct Solver {
         for (int s2 = 0; s2 < poll; ++s2)
           for (int f = 0; f < SCOCG_K_FAMILIES; ++f) {
             if (f == SCOCG_K_PROJ) continue;  // fused into the MU launch
+            if (o.timing == 2 && f != SCOCG_K_UPDATE) continue;
             float t = 0.f;
             hipEvent_t* e = ev_of(s2);
             HIPCHK(hipEventElapsedTime(&t, e[2 * f], e[2 * f + 1]));
@@ -982,6 +988,7 @@ int scocg_solve(scocg_handle h, int32_t K, const double* z, int32_t R, const int
     require(std::isfinite(o.tol), "non-finite tol");
     if (o.max_iter <= 0) o.max_iter = 100000;
     require(o.init_seed >= -1 && o.init_seed < K, "init_seed out of range");
+    require(o.timing >= 0 && o.timing <= 2, "timing must be 0, 1 or 2");
     if (!o.full) {
       if (s_idx) {
         require(nS >= 1, "nS must be >= 1 with s_idx");

@@ -119,7 +119,7 @@ class Handle:
         self.last = None
 
     def solve(self, z, rhs_idx, s_idx=None, tol=1e-10, max_iter=100000, init_seed=-1,
-              seed_switch=True, full=False, refine=0, poll_every=0, use_graph=False, timing=False,
+              seed_switch=True, full=False, refine=0, poll_every=0, use_graph=False, timing=0,
               tile=0, zchunk=0):
         """scocg_solve; returns (rc, report dict with [K, R] arrays)."""
         lib = load()
@@ -133,7 +133,7 @@ class Handle:
             nS = sp.size
         o = SolveOpts(float(tol), int(max_iter), int(init_seed), int(bool(seed_switch)),
                       int(bool(full)), int(refine), int(poll_every), int(bool(use_graph)),
-                      int(bool(timing)), int(tile), int(zchunk))
+                      int(timing), int(tile), int(zchunk))
         iters = np.zeros((K, R), np.int64)
         est = np.zeros((K, R))
         tres = np.zeros((K, R))

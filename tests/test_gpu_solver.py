@@ -185,15 +185,29 @@ def test_projected_rows_equal_full_rows_bitwise(dev, tiny_full):
 
 
 def test_repeatable_and_graph_replay_bitwise(dev):
+    """Direct launches, graph replays and both event-timing modes give the same bits;
+    the timing modes report launches for the families they bracket."""
     p = W.tiny_fp64()
     h = scocg.create_from_problem(p, precision=scocg.FP64)
     outs = []
-    for g in (False, False, True, True):
-        rc, rep = h.solve(p.z, p.rhs_idx, tol=1e-10, use_graph=g, poll_every=8)
+    for g, tm in ((False, 0), (False, 0), (True, 0), (True, 0), (False, 1), (True, 2)):
+        rc, rep = h.solve(p.z, p.rhs_idx, tol=1e-10, use_graph=g, poll_every=8, timing=tm)
+        assert rc == scocg.OK
         outs.append((h.green_columns(), rep["iters"].copy()))
+        n = rep["kernel_launches"]
+        if tm == 0:
+            assert sum(n.values()) == 0
+        elif tm == 1:
+            assert n["proj"] == 0 and all(n[f] > 0 for f in ("mu", "alpha", "update", "control", "shift"))
+            assert n["update"] == n["mu"] and rep["kernel_ms"]["update"] > 0
+        else:
+            assert n["update"] > 0 and sum(n.values()) == n["update"]
+            assert rep["kernel_ms"]["update"] > 0
     for G, it in outs[1:]:
         assert np.array_equal(G, outs[0][0])
         assert np.array_equal(it, outs[0][1])
+    with pytest.raises(scocg.ScocgError):
+        h.solve(p.z, p.rhs_idx, tol=1e-10, timing=3)
     h.destroy()
 
 
