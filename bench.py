@@ -42,7 +42,7 @@ def parse():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--cpu-energies", type=int, default=8)
     ap.add_argument("--cpu-cols", type=int, default=8)
-    ap.add_argument("--cpu-iters", type=int, default=128)
+    ap.add_argument("--cpu-iters", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--max-iter", type=int, default=0,
                     help="cap the seed iterations (short counter-collection runs only)")
@@ -51,6 +51,8 @@ def parse():
                          "MiB whose counter readings scale the HBM byte counters")
     ap.add_argument("--no-diag", action="store_true",
                     help="skip the untimed per-family timing solve")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the mixed-vs-FP64 comparison on the 16x16x24 all-plane workload")
     return ap.parse_args()
 
 
@@ -111,6 +113,47 @@ def cpu_baseline(p, n_energies, n_cols, iters_cap, tol, mean_iters):
                       f"{rate:.1f} pair-iterations/s, divided by the workload's mean of "
                       f"{mean_iters:.0f} iterations per converged pair (from the GPU solve's "
                       f"per-pair counts)"}
+
+
+def mixed_vs_fp64(tol):
+    """Both precisions on the 16x16x24 workload with all 256 points of the iz=0 plane as
+    columns and 256 energies, full storage so every pair gets its FP64 true residual.
+    A solve counts when that true residual is <= 1.05 tol (the FP64 path stops on its
+    recursive estimate; 5 % covers the rounding gap).  The mixed path's time includes
+    its FP64 checks and refinement passes; the FP64 path's includes its check."""
+    import torch
+    from paper_1502_00081_amd import scocg, workload
+    p = workload.tiny_mixed()
+    K, R, N = p.z.size, p.rhs_idx.size, p.n
+    res, G = {}, {}
+    for name, prec, refine in (("fp64", scocg.FP64, 0), ("mixed", scocg.MIXED, 3)):
+        h = scocg.create_from_problem(p, precision=prec, stream=torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, rep = h.solve(p.z, p.rhs_idx, tol=tol, full=True, refine=refine, use_graph=True)
+        G[name] = torch.empty((K, R, N), dtype=torch.complex128, device="cuda")
+        h.green_columns(G[name])
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        h.destroy()
+        tr = rep["true_resid"]
+        ok = int((tr <= 1.05 * tol).sum())
+        res[name] = {"solves_per_s": ok / wall, "solves": ok, "pairs": K * R,
+                     "wall_ms": wall * 1e3, "solve_ms_device": rep["solve_ms"],
+                     "seed_iters": int(rep["seed_iters"]), "refined_pairs": int(rep["refined"]),
+                     "true_resid_max": float(tr.max()), "true_resid_median": float(np.median(tr))}
+        say(f"mixed-vs-fp64 {name}: {ok}/{K * R} pairs <= tol in {wall * 1e3:.0f} ms "
+            f"({rep['seed_iters']} seed iterations, {rep['refined']} refined)")
+    ref = G["fp64"]
+    err = (torch.linalg.vector_norm(G["mixed"] - ref, dim=2) /
+           torch.linalg.vector_norm(ref, dim=2)).cpu().numpy()
+    del G, ref
+    res["mixed"]["rel_err_vs_fp64_max"] = float(err.max())
+    res["mixed"]["rel_err_vs_fp64_median"] = float(np.median(err))
+    res["mixed_over_fp64"] = res["mixed"]["solves_per_s"] / res["fp64"]["solves_per_s"]
+    res["workload"] = {"name": p.name, "grid": [p.nx, p.ny, p.nz], "energies": K, "rhs": R,
+                       "storage": "full", "tol": tol}
+    return res
 
 
 def main():
@@ -210,6 +253,9 @@ def main():
         torch.cuda.synchronize()
         line["ms_per_step_graph_replay"] = (time.perf_counter() - tg) * 1e3
     h.destroy()
+    del out
+    if not a.no_mixed:
+        line["mixed_vs_fp64"] = mixed_vs_fp64(a.tol)
     if not a.no_cpu_baseline:
         say(f"cpu baseline: oracle on {a.cpu_energies}x{a.cpu_cols} pairs, "
             f"{a.cpu_iters} iterations each")

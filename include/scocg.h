@@ -58,6 +58,9 @@ extern "C" {
 #define SCOCG_PAIR_CONVERGED 0
 #define SCOCG_PAIR_MAXITER 1
 #define SCOCG_PAIR_BREAKDOWN 2
+#define SCOCG_PAIR_STALLED 4   /* SCOCG_MIXED only: the complex64 recurrence stopped
+                                  improving above tol (and, with full = 1, the FP64
+                                  true residual still misses tol after refinement) */
 
 /* output element type for scocg_green_columns */
 #define SCOCG_C128 0
@@ -100,7 +103,9 @@ typedef struct {
     int32_t full;        /* 1: S = all N rows (full x^{(k)} kept; enables the true residual) */
     int32_t refine;      /* SCOCG_MIXED with full = 1: max refinement passes for pairs
                             whose FP64 true residual misses tol (0 = check only, -1 = skip
-                            the check); ignored for SCOCG_FP64 */
+                            the check); ignored for SCOCG_FP64.  With the check, a
+                            SCOCG_MIXED pair is SCOCG_PAIR_CONVERGED iff its FP64 true
+                            residual is <= tol */
     int32_t poll_every;  /* seed iterations between host convergence polls; 0 -> auto */
     int32_t use_graph;   /* 1: replay the per-poll iterations as one captured hipGraph */
     int32_t timing;      /* 1: bracket every kernel launch with HIP events and report the

@@ -68,6 +68,7 @@ struct ColState {
   double2 scale[2];    // stored Krylov buffer b holds r / scale[b] (lazy seed-switch rescale)
   double2 ar, ah, ap;  // r_{n+1} = ar r^st_n + ah (H r^st_n) + ap r^st_{n-1}
   double bnorm;        // ||b||
+  double tol;          // per-column tolerance (0: the solve's tol)
   int32_t seed;        // seed shift index
   int32_t done;        // column finished
   int32_t breakdown;   // column hit a vanishing bilinear form
@@ -81,9 +82,10 @@ struct ShiftState {
   double2 pi;       // pi_n
   double est;       // ||r_n|| / |pi_n| / ||b||
   int32_t iters;    // iteration at which the pair froze
-  int32_t status;   // 0 converged, 1 max-iter, 2 breakdown, 3 unused column
+  int32_t status;   // 0 converged, 1 max-iter, 2 breakdown, 3 unused column, 4 stalled
   int32_t active;   // still iterating
-  int32_t pad_;
+  int32_t best_it;  // iteration of the last halving of est (stagnation test)
+  double best;      // est at that iteration
 };
 
 struct ShiftCoef {
@@ -94,7 +96,7 @@ struct ShiftCoef {
   int32_t pad_[3];
 };
 
-enum { ST_CONVERGED = 0, ST_MAXITER = 1, ST_BREAKDOWN = 2, ST_UNUSED = 3 };
+enum { ST_CONVERGED = 0, ST_MAXITER = 1, ST_BREAKDOWN = 2, ST_UNUSED = 3, ST_STALLED = 4 };
 
 // Real stencil coefficients, by value in the kernel argument segment.
 template <typename T> struct Coefs {
@@ -699,13 +701,17 @@ struct ControlArgs {
   double tol;
   int64_t max_iter;
   int seed_switch;
+  int stall;                // > 0 (complex64 recurrences): freeze a pair whose est is
+                            // below 1e-2 and has not halved in max(stall, n/2) iterations
+  double floor_est;         // complex64 recurrences: freeze at est <= max(tol, floor_est)
 };
 
 // One workgroup per column block (B columns x K shifts):
 //   beta_n = rho_{n+1} / rho_n                                            (Eq. A6)
 //   pi_{n+1} = (1 + c_n + alpha_n sigma) pi_n - c_n pi_{n-1}, sigma = z_k - z_s   (Eq. A8)
 //   alpha^(k)_n = pi_n/pi_{n+1} alpha_n,  beta^(k)_n = (pi_n/pi_{n+1})^2 beta_n  (Eqs. A9-A10)
-//   freeze (k, j) once ||r_{n+1}|| / |pi_{n+1}| <= tol ||b||; compact the active list;
+//   freeze (k, j) once ||r_{n+1}|| / |pi_{n+1}| <= tol ||b|| (or, for complex64
+//   vectors, once that estimate stops halving); compact the active list;
 //   seed switch to the active shift of smallest |pi_{n+1}| once the seed froze (Eq. A13).
 // Thread t always serves column t % B (CT is a multiple of B), so every
 // per-column reduction is one fixed-order tree over the CT/B lanes of that
@@ -731,8 +737,8 @@ __global__ __launch_bounds__(CT) void k_control(ControlArgs a) {
   __shared__ double sh_nu[CT];
   __shared__ int s_k[CT];
   __shared__ double2 s_alpha[B], s_beta[B], s_c[B], s_zs[B], s_fn[B], s_fc[B];
-  __shared__ double s_nrm[B];
-  __shared__ int s_live[B], s_cnt_col[B], s_argmin[B], s_sw[B];
+  __shared__ double s_nrm[B], s_tol[B];
+  __shared__ int s_live[B], s_sw[B];
   __shared__ int s_wsum[NWAVE];
   __shared__ double2 s_rhon[B];
   __shared__ int s_any_sw;
@@ -769,6 +775,7 @@ __global__ __launch_bounds__(CT) void k_control(ControlArgs a) {
       s_c[tid] = cs.c;
       s_zs[tid] = cs.zs;
       s_nrm[tid] = sqrt(sh_nu[tid]) / cs.bnorm;
+      s_tol[tid] = cs.tol > 0.0 ? cs.tol : a.tol;
     }
     if (tid == 0) s_any_sw = 0;
   }
@@ -806,10 +813,26 @@ __global__ __launch_bounds__(CT) void k_control(ControlArgs a) {
         st.status = ST_BREAKDOWN;
         st.iters = n + 1;
         cf.upd = 0;
-      } else if (st.est <= a.tol) {
+      } else if (st.est <= s_tol[c]) {
         st.active = 0;
         st.status = ST_CONVERGED;
         st.iters = n + 1;
+      } else if (a.stall > 0) {
+        // complex64 recurrences level off near u32 times the condition number: stop
+        // at the floor, or once the estimate stalls past the initial plateau, and
+        // leave the pair to the FP64-checked refinement
+        if (st.est <= a.floor_est) {
+          st.active = 0;
+          st.status = ST_STALLED;
+          st.iters = n + 1;
+        } else if (st.est <= 0.5 * st.best) {
+          st.best = st.est;
+          st.best_it = n + 1;
+        } else if (st.est < 1e-2 && n + 1 - st.best_it > max(a.stall, (n + 1) / 2)) {
+          st.active = 0;
+          st.status = ST_STALLED;
+          st.iters = n + 1;
+        }
       }
       a.sh[o] = st;
     } else if (st.active && brk_c) {
@@ -880,9 +903,11 @@ __global__ __launch_bounds__(CT) void k_control(ControlArgs a) {
     __syncthreads();
   }
   int cnt_c = 0, argmin_c = 0;
+  double pimin_c = INFINITY;
   if (tid < B) {
     cnt_c = (int)sh_rho[tid].x;
     argmin_c = s_k[tid];
+    pimin_c = sh_nu[tid];
   }
   __syncthreads();  // sh_rho is reused below
 
@@ -896,7 +921,12 @@ __global__ __launch_bounds__(CT) void k_control(ControlArgs a) {
       double2 alpha = s_alpha[tid], beta = s_beta[tid];
       double2 rho_new = s_rhon[tid];
       const ShiftState& sst = a.sh[((int64_t)cb * K + cs.seed) * B + tid];
-      if (a.seed_switch && !sst.active && cnt_c > 0 && !last) sw = argmin_c;
+      // complex64 vectors also switch while the seed is active, as soon as another
+      // shift's residual is 4x the seed's (|pi| < 1/4; the seed's own pi is 1): the
+      // seed then never sinks towards the rounding floor of its stored vectors, which
+      // a later rebase by 1/pi would amplify
+      const bool early = a.stall > 0 && sst.active && pimin_c < 0.25;
+      if (a.seed_switch && (!sst.active || early) && cnt_c > 0 && !last) sw = argmin_c;
       if (sw >= 0) {
         const ShiftState& t = a.sh[((int64_t)cb * K + sw) * B + tid];
         const double2 fn = t.pi, fc = t.pi_prev;  // pi^{(s,s~)}_{n+1}, pi^{(s,s~)}_n
@@ -1030,10 +1060,11 @@ __global__ void k_init_xp(double2* x, typename cplx_of<T>::type* p, const int32_
 }
 
 // z: [K] energies shared by every column, or (zpc != null, K == 1) one energy per
-// column zpc[cb*B + c].
+// column zpc[cb*B + c]; tolc (optional, [R]): per-column tolerances.
 template <int B>
 __global__ void k_init_state(ColState* cols, ShiftState* sh, ShiftCoef* coef, double2* zcol,
                              const double2* __restrict__ z, const double2* __restrict__ zpc,
+                             const double* __restrict__ tolc,
                              int K, int nb, int R, int seed0, int32_t* list, int32_t* cnt,
                              int32_t* k5cnt, int32_t* blk_active, int32_t* blk_iter) {
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1050,7 +1081,8 @@ __global__ void k_init_state(ColState* cols, ShiftState* sh, ShiftCoef* coef, do
     st.iters = 0;
     st.active = j < R;
     st.status = j < R ? ST_MAXITER : ST_UNUSED;
-    st.pad_ = 0;
+    st.best_it = 0;
+    st.best = 1.0;
     sh[gid] = st;
     ShiftCoef cf{};
     cf.upd = 0;
@@ -1073,6 +1105,7 @@ __global__ void k_init_state(ColState* cols, ShiftState* sh, ShiftCoef* coef, do
     cs.scale[0] = mk(1, 0);
     cs.scale[1] = mk(1, 0);
     cs.bnorm = 1.0;
+    cs.tol = (tolc && j < R) ? tolc[j] : 0.0;
     cs.seed = seed0;
     cs.done = j >= R;
     cols[j] = cs;
@@ -1279,10 +1312,13 @@ template <int B, int BS>
 __global__ void k_add_correction(double2* __restrict__ xout, const double2* __restrict__ d,
                                  const int32_t* __restrict__ src_kb,
                                  const int32_t* __restrict__ src_c,
-                                 const double* __restrict__ back, int R, int64_t N) {
+                                 const double* __restrict__ back,
+                                 const ShiftState* __restrict__ inner, int R, int64_t N) {
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= (int64_t)R * N) return;
   const int j = (int)(gid / N);
+  // a correction whose inner solve did not at least halve its residual is dropped
+  if (!(inner[j].est < 0.5)) return;
   const int64_t pnt = gid % N;
   const int cb = j / B, c = j % B;
   const double2 dv = d[((int64_t)cb * N + pnt) * B + c];

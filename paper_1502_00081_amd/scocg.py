@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libscocg.so")
 OK, EINVAL, ENOMEM, EHIP, ENOSOLVE = 0, -1, -2, -3, -4
 NOT_ALL_CONVERGED, BREAKDOWN = 1, 2
 FP64, MIXED = 0, 1
-PAIR_CONVERGED, PAIR_MAXITER, PAIR_BREAKDOWN = 0, 1, 2
+PAIR_CONVERGED, PAIR_MAXITER, PAIR_BREAKDOWN, PAIR_STALLED = 0, 1, 2, 4
 C128, C64 = 0, 1
 
 EXPORTS = ("scocg_create", "scocg_solve", "scocg_green_columns", "scocg_apply_h",

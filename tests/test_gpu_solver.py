@@ -364,3 +364,37 @@ def test_mixed_refinement_reaches_fp64_tolerance(dev):
     eta = p.z.imag.min()
     d = np.linalg.norm(G - ref, axis=2)
     assert (d <= (tr + 1e-13) / eta).all()
+
+
+def test_mixed_all_plane_columns_certified_by_fp64_residual(dev):
+    """All 256 points of the iz=0 plane as columns, 16 energies: complex64 recurrences
+    stop at their floor (status stalled, FP64 true residual above tol), then the
+    correction passes certify every pair; sampled pairs match the oracle within the
+    resolvent bound."""
+    base = W.tiny_mixed()
+    p = base.with_(z=base.z[::16])
+    tol = 1e-8
+    h = scocg.create_from_problem(p, precision=scocg.MIXED)
+    rc0, rep0 = h.solve(p.z, p.rhs_idx, tol=tol, full=True, refine=0)
+    tr0, st0 = rep0["true_resid"], rep0["status"]
+    say(f"mixed all-plane, no refinement: rc={rc0}, true residual median {np.median(tr0):.2e} "
+        f"max {tr0.max():.2e}")
+    assert rc0 == scocg.NOT_ALL_CONVERGED
+    assert np.array_equal(st0 == scocg.PAIR_CONVERGED, tr0 <= tol)
+    assert ((st0 == scocg.PAIR_CONVERGED) | (st0 == scocg.PAIR_STALLED)).all()
+    rc, rep = h.solve(p.z, p.rhs_idx, tol=tol, full=True, refine=3)
+    G = h.green_columns()
+    h.destroy()
+    say(f"mixed all-plane, refined {rep['refined']} pairs: max {rep['true_resid'].max():.2e}")
+    assert rc == scocg.OK
+    assert (rep["status"] == scocg.PAIR_CONVERGED).all()
+    assert (rep["true_resid"] <= tol).all()
+    rng = np.random.default_rng(5)
+    pairs = [(int(k), int(j)) for k, j in zip(rng.integers(0, p.z.size, 12),
+                                              rng.integers(0, p.rhs_idx.size, 12))]
+    rows = np.arange(p.n)
+    ref, _, _, _ = oracle.cocg_unit_columns(p, p.z, p.rhs_idx, rows, pairs, tol=1e-12)
+    eta = p.z.imag.min()
+    for i, (k, j) in enumerate(pairs):
+        d = np.linalg.norm(G[k, j] - ref[i])
+        assert d <= (rep["true_resid"][k, j] + 1e-12) / eta, (k, j, d)
