@@ -51,6 +51,8 @@ def parse():
                          "MiB whose counter readings scale the HBM byte counters")
     ap.add_argument("--no-diag", action="store_true",
                     help="skip the untimed per-family timing solve")
+    ap.add_argument("--fixed-shape", action="store_true",
+                    help="default launch shape instead of the autotuned one")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed-vs-FP64 comparison on the 16x16x24 all-plane workload")
     return ap.parse_args()
@@ -173,6 +175,8 @@ def main():
     K, R = p.z.size, p.rhs_idx.size
     out = torch.empty((K, R, R), dtype=torch.complex128, device="cuda")
     kw = dict(tol=a.tol, timing=2)
+    if not a.fixed_shape:  # autotuned in the first (warmup) solve, cached in the handle
+        kw.update(tile=scocg.AUTO, zchunk=scocg.AUTO, shift_chunk=scocg.AUTO)
     if a.max_iter > 0:
         kw["max_iter"] = a.max_iter
     if a.calibrate_copy_mib > 0:
@@ -185,6 +189,10 @@ def main():
         say(f"calibration copy: {nbytes} bytes read, {nbytes} bytes written")
         del src, dst
     say(f"workload {p.name}: N={p.n}, K={K}, R={R}, precision {a.precision}")
+    if not a.fixed_shape:
+        rc, rep = h.solve(p.z, p.rhs_idx, **dict(kw, max_iter=16, timing=0))
+        say(f"autotuned launch shape: tile {rep['tile']} zchunk {rep['zchunk']} shift chunk "
+            f"{rep['shift_chunk']} ({rep['tune_ms']:.0f} ms of trials)")
     for i in range(a.warmup):
         rc, rep = h.solve(p.z, p.rhs_idx, **kw)
         h.green_columns(out)
@@ -234,6 +242,9 @@ def main():
                      f"HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated) over "
                      f"launches whose algorithmic bytes are {traffic_alg:.4g}: ratio "
                      f"{traffic / traffic_alg:.3f}"},
+        "launch_shape": {"tile": reps[-1]["tile"], "zchunk": reps[-1]["zchunk"],
+                         "shift_chunk": reps[-1]["shift_chunk"],
+                         "autotuned": not a.fixed_shape},
         "seed_iters": int(reps[-1]["seed_iters"]),
         "solve_ms_device": float(np.mean([r["solve_ms"] for r in reps])),
     }

@@ -115,9 +115,22 @@ typedef struct {
     int32_t tile;        /* stencil workgroup shape, x-y tile TX x TY and threads per group
                             (0 -> 1 for SCOCG_FP64, 3 for SCOCG_MIXED). SCOCG_FP64: 1 = 16x8/1024, 2 = 16x4/512,
                             3 = 8x8/512, 4 = 16x8/512.  SCOCG_MIXED: 1 = 16x8/1024,
-                            2 = 16x4/512, 3 = 8x8/1024, 4 = 8x8/512.  nf < 4 always uses 1 */
-    int32_t zchunk;      /* z planes per stencil workgroup (0 -> chosen from the grid size) */
+                            2 = 16x4/512, 3 = 8x8/1024, 4 = 8x8/512.  nf < 4 always uses 1.
+                            SCOCG_AUTO: autotuned (see below) */
+    int32_t zchunk;      /* z planes per stencil workgroup (0 -> chosen from the grid size;
+                            SCOCG_AUTO: autotuned) */
+    int32_t shift_chunk; /* energies per workgroup of the x^(k), p^(k) update: 1, 4 or 16
+                            (0 -> 4; SCOCG_AUTO: autotuned) */
 } scocg_solve_opts;
+
+/* Autotuning: any of tile, zchunk, shift_chunk = SCOCG_AUTO makes scocg_solve time
+   short trial runs (16 seed iterations from the initial state of this very problem)
+   of each candidate launch shape -- the 4 tile shapes x up to 4 z-chunk lengths around
+   the default, then 3 shift chunks -- before the solve proper, keep the fastest, and
+   cache it in the handle for this (column blocks, energies, rows) shape; later solves
+   of that shape reuse it.  Trials run outside the timed region (scocg_report.tune_ms
+   gives their cost, 0 when cached). */
+#define SCOCG_AUTO (-1)
 
 /* kernel families of one seed iteration (index into scocg_report.kernel_ms) */
 #define SCOCG_K_PROJ 0     /* (reported as 0: the projector contraction runs inside SCOCG_K_MU) */
@@ -143,6 +156,11 @@ typedef struct {
     int32_t n_blocks;    /* out: column blocks */
     double kernel_ms[SCOCG_K_FAMILIES];      /* out (timing != 0): summed launch durations */
     int64_t kernel_launches[SCOCG_K_FAMILIES]; /* out (timing != 0): launches timed */
+    int32_t tile_used;   /* out: launch shape of the solve (after autotuning) */
+    int32_t zchunk_used;
+    int32_t shift_chunk_used;
+    int32_t tuned;       /* out: 1 if this call ran the autotuning trials */
+    double tune_ms;      /* out: device time of the autotuning trials */
 } scocg_report;
 
 /*
@@ -177,6 +195,11 @@ void scocg_destroy(scocg_handle h);
 
 /* Thread-local description of the last error ("" if none). */
 const char *scocg_last_error(void);
+
+/* Size in bytes of the ABI structs, for bindings to check their mirrors:
+   which = 0 scocg_grid, 1 scocg_solve_opts, 2 scocg_report; 0 for any other
+   value.  Needs no GPU. */
+int64_t scocg_struct_size(int32_t which);
 
 #ifdef __cplusplus
 }

@@ -11,11 +11,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <stdexcept>
 #include <string>
@@ -112,6 +114,7 @@ struct scocg_ctx {
     bool ok = false;
     int B = 0, nb = 0, K = 0, R = 0, nS = 0, nwg = 0;
     StencilGrid g{};
+    int kch = 4;  // energies per workgroup of k_shift
     bool full = false;
     DevBuf r0, r1, z, cols, sh, coef, list, cnt, k5cnt, blk_active, blk_iter, rhs, srow, x, p,
         dc, qa, part0, part1;
@@ -121,6 +124,8 @@ struct scocg_ctx {
     }
   };
   std::unique_ptr<Solve> last;
+  // autotuned launch shapes per (B, column blocks, energies, rows): {tile, zchunk, kch}
+  std::map<std::array<int64_t, 4>, std::array<int32_t, 3>> tuned;
 };
 
 namespace {
@@ -382,6 +387,18 @@ struct Solver {
     HIPCHK(hipEventRecord(ev[2 * fam + end], h.stream));
   }
 
+  // x^(k), p^(k) update, KCH energies per workgroup
+  template <int KCH>
+  void launch_shift(cT* rn, int par) {
+    const int64_t rows = (int64_t)S.nS * B;
+    dim3 g5(nblocks(rows, WG), nblocks(S.K, KCH), S.nb);
+    hipLaunchKernelGGL((k_shift<T, B, KCH>), g5, dim3(WG), 0, h.stream, plane0(rn), bstride(),
+                       S.full ? nullptr : S.srow.as<int32_t>(), S.nS,
+                       S.list.as<int32_t>() + (int64_t)par * S.nb * S.K, S.k5cnt.as<int32_t>(),
+                       S.K, S.coef.as<ShiftCoef>(), S.x.as<double2>(), S.p.as<cT>());
+    KCHK();
+  }
+
   void one_iteration(int cur, int par, const scocg_solve_opts& o, hipEvent_t* ev) {
     cT* rc = (cur ? S.r1 : S.r0).template as<cT>();
     cT* rn = (cur ? S.r0 : S.r1).template as<cT>();
@@ -425,14 +442,11 @@ struct Solver {
     KCHK();
     mark(ev, SCOCG_K_CONTROL, 1);
     mark(ev, SCOCG_K_SHIFT, 0);
-    constexpr int KCH = 4;
-    const int64_t rows = (int64_t)S.nS * B;
-    dim3 g5(nblocks(rows, WG), nblocks(S.K, KCH), S.nb);
-    hipLaunchKernelGGL((k_shift<T, B, KCH>), g5, dim3(WG), 0, h.stream, plane0(rn), bstride(),
-                       S.full ? nullptr : S.srow.as<int32_t>(), S.nS,
-                       S.list.as<int32_t>() + (int64_t)par * S.nb * S.K, S.k5cnt.as<int32_t>(),
-                       S.K, S.coef.as<ShiftCoef>(), S.x.as<double2>(), S.p.as<cT>());
-    KCHK();
+    switch (S.kch) {
+      case 1: launch_shift<1>(rn, par); break;
+      case 16: launch_shift<16>(rn, par); break;
+      default: launch_shift<4>(rn, par); break;
+    }
     mark(ev, SCOCG_K_SHIFT, 1);
   }
 
@@ -519,6 +533,7 @@ struct Solver {
     const int nb = S.nb;
     S.g = plan(nb, o.tile, o.zchunk);
     S.nwg = S.g.nwg;
+    S.kch = o.shift_chunk > 0 ? o.shift_chunk : 4;
     const size_t vec = (size_t)nb * bstride() * sizeof(cT);
     S.r0.alloc(vec);
     S.r1.alloc(vec);
@@ -652,6 +667,100 @@ struct Solver {
     return it;
   }
 
+  // switch the stencil launch shape, growing the partial-sum buffers if needed
+  void set_grid(const StencilGrid& g) {
+    const size_t need = (size_t)S.nb * g.nwg * B;
+    if (S.part0.bytes < need * sizeof(double2)) S.part0.alloc(need * sizeof(double2));
+    if (S.part1.bytes < need * sizeof(double)) S.part1.alloc(need * sizeof(double));
+    S.g = g;
+    S.nwg = g.nwg;
+  }
+
+  // Device time per seed iteration of `iters` iterations from the initial state
+  double trial(const double2* zk, int seed0, const scocg_solve_opts& o, int iters) {
+    scocg_solve_opts ot = o;
+    ot.max_iter = iters;
+    ot.timing = 0;
+    ot.use_graph = 0;
+    ot.poll_every = iters;
+    init_unit(zk, seed0);
+    hipEvent_t a, b;
+    HIPCHK(hipEventCreate(&a));
+    HIPCHK(hipEventCreate(&b));
+    HIPCHK(hipEventRecord(a, h.stream));
+    double km[SCOCG_K_FAMILIES] = {0};
+    int64_t kc[SCOCG_K_FAMILIES] = {0};
+    const int64_t n = iterate(ot, km, kc);
+    HIPCHK(hipEventRecord(b, h.stream));
+    HIPCHK(hipEventSynchronize(b));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, a, b));
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return 1e3 * ms / (double)std::max<int64_t>(n, 1);
+  }
+
+  // Autotuning: time each candidate stencil shape (tile x z-chunk), then each shift
+  // chunk, on this problem; keep the fastest.  Returns the device time spent.
+  double tune(const double2* zk, int seed0, const scocg_solve_opts& o, bool want_tile,
+              bool want_zc, bool want_kch) {
+    constexpr int kIters = 16;
+    float total = 0.f;
+    hipEvent_t a, b;
+    HIPCHK(hipEventCreate(&a));
+    HIPCHK(hipEventCreate(&b));
+    HIPCHK(hipEventRecord(a, h.stream));
+    if (want_tile || want_zc) {
+      std::vector<int> vs;
+      if (want_tile && h.nf == 4) vs = {1, 2, 3, 4};
+      else vs = {want_tile ? 1 : std::max(o.tile, 0)};
+      double best = INFINITY;
+      StencilGrid bg = S.g;
+      for (int v : vs) {
+        const StencilGrid g0 = plan(S.nb, v, want_zc ? 0 : o.zchunk);
+        std::vector<int> zcs = {g0.zc};
+        if (want_zc)
+          for (int zc : {g0.zc / 2, g0.zc * 2, g0.zc * 4})
+            if (zc >= 4 && zc <= h.nz) zcs.push_back(zc);
+        std::sort(zcs.begin(), zcs.end());
+        zcs.erase(std::unique(zcs.begin(), zcs.end()), zcs.end());
+        for (int zc : zcs) {
+          const StencilGrid g = plan(S.nb, v, zc);
+          set_grid(g);
+          const double us = trial(zk, seed0, o, kIters);
+          if (trace_on())
+            fprintf(stderr, "[scocg] tune tile %d zchunk %d: %.1f us/iteration\n", g.variant,
+                    g.zc, us);
+          if (us < best) {
+            best = us;
+            bg = g;
+          }
+        }
+      }
+      set_grid(bg);
+    }
+    if (want_kch) {
+      double best = INFINITY;
+      int bk = 4;
+      for (int kch : {1, 4, 16}) {
+        S.kch = kch;
+        const double us = trial(zk, seed0, o, kIters);
+        if (trace_on()) fprintf(stderr, "[scocg] tune shift chunk %d: %.1f us/iteration\n", kch, us);
+        if (us < best) {
+          best = us;
+          bk = kch;
+        }
+      }
+      S.kch = bk;
+    }
+    HIPCHK(hipEventRecord(b, h.stream));
+    HIPCHK(hipEventSynchronize(b));
+    HIPCHK(hipEventElapsedTime(&total, a, b));
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return total;
+  }
+
   void release_workspace() {
     S.r0.release();
     S.r1.release();
@@ -706,6 +815,8 @@ struct Solver {
     oi.full = 1;
     oi.init_seed = 0;
     oi.tile = 0;
+    oi.zchunk = 0;
+    oi.shift_chunk = 0;
     oi.max_iter = cap;
     oi.tol = std::min(0.5, std::max(1e-12, 0.25 * o.tol / tmax));  // per-column tolc rules
     oi.timing = 0;
@@ -789,12 +900,31 @@ struct Solver {
     alloc_state(K, R, full, nS, o);
     const int nb = S.nb;
     const size_t nkb = (size_t)nb * K * B;
+    const int seed0 = o.init_seed < 0 ? K / 2 : o.init_seed;
+
+    // autotuning (outside the timed region; cached per shape in the handle)
+    const bool auto_tile = o.tile == SCOCG_AUTO, auto_zc = o.zchunk == SCOCG_AUTO,
+               auto_kch = o.shift_chunk == SCOCG_AUTO;
+    double tune_ms = 0.0;
+    int tuned_now = 0;
+    if (auto_tile || auto_zc || auto_kch) {
+      const std::array<int64_t, 4> key{B, nb, K, S.nS};
+      auto it = h.tuned.find(key);
+      if (it != h.tuned.end()) {
+        set_grid(plan(nb, auto_tile ? it->second[0] : o.tile, auto_zc ? it->second[1] : o.zchunk));
+        if (auto_kch) S.kch = it->second[2];
+      } else {
+        tune_ms = tune(zk.as<double2>(), seed0, o, auto_tile, auto_zc, auto_kch);
+        tuned_now = 1;
+        h.tuned[key] = {S.g.variant, S.g.zc, S.kch};
+      }
+    }
 
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     HIPCHK(hipEventRecord(e0, st));
-    init_unit(zk.as<double2>(), o.init_seed < 0 ? K / 2 : o.init_seed);
+    init_unit(zk.as<double2>(), seed0);
     double kms[SCOCG_K_FAMILIES] = {0};
     int64_t kcount[SCOCG_K_FAMILIES] = {0};
     const int64_t it_main = iterate(o, kms, kcount);
@@ -878,6 +1008,11 @@ struct Solver {
         rep->kernel_ms[f] = kms[f];
         rep->kernel_launches[f] = kcount[f];
       }
+      rep->tile_used = S.g.variant;
+      rep->zchunk_used = S.g.zc;
+      rep->shift_chunk_used = S.kch;
+      rep->tuned = tuned_now;
+      rep->tune_ms = tune_ms;
     }
     S.ok = true;
     return rc;
@@ -1017,6 +1152,11 @@ int scocg_solve(scocg_handle h, int32_t K, const double* z, int32_t R, const int
     if (o.max_iter <= 0) o.max_iter = 100000;
     require(o.init_seed >= -1 && o.init_seed < K, "init_seed out of range");
     require(o.timing >= 0 && o.timing <= 2, "timing must be 0, 1 or 2");
+    require(o.tile >= SCOCG_AUTO && o.tile <= 4, "tile must be SCOCG_AUTO or 0..4");
+    require(o.zchunk >= SCOCG_AUTO, "zchunk must be SCOCG_AUTO or >= 0");
+    require(o.shift_chunk == SCOCG_AUTO || o.shift_chunk == 0 || o.shift_chunk == 1 ||
+                o.shift_chunk == 4 || o.shift_chunk == 16,
+            "shift_chunk must be SCOCG_AUTO, 0, 1, 4 or 16");
     if (!o.full) {
       if (s_idx) {
         require(nS >= 1, "nS must be >= 1 with s_idx");
@@ -1097,5 +1237,14 @@ void scocg_destroy(scocg_handle h) {
 }
 
 const char* scocg_last_error(void) { return g_err.c_str(); }
+
+int64_t scocg_struct_size(int32_t which) {
+  switch (which) {
+    case 0: return (int64_t)sizeof(scocg_grid);
+    case 1: return (int64_t)sizeof(scocg_solve_opts);
+    case 2: return (int64_t)sizeof(scocg_report);
+    default: return 0;
+  }
+}
 
 }  // extern "C"

@@ -23,7 +23,8 @@ PAIR_CONVERGED, PAIR_MAXITER, PAIR_BREAKDOWN, PAIR_STALLED = 0, 1, 2, 4
 C128, C64 = 0, 1
 
 EXPORTS = ("scocg_create", "scocg_solve", "scocg_green_columns", "scocg_apply_h",
-           "scocg_destroy", "scocg_last_error")
+           "scocg_destroy", "scocg_last_error", "scocg_struct_size")
+AUTO = -1  # SCOCG_AUTO: autotuned launch shape
 
 
 class Grid(C.Structure):
@@ -35,7 +36,7 @@ class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int64), ("init_seed", C.c_int32),
                 ("seed_switch", C.c_int32), ("full", C.c_int32), ("refine", C.c_int32),
                 ("poll_every", C.c_int32), ("use_graph", C.c_int32), ("timing", C.c_int32),
-                ("tile", C.c_int32), ("zchunk", C.c_int32)]
+                ("tile", C.c_int32), ("zchunk", C.c_int32), ("shift_chunk", C.c_int32)]
 
 
 class Report(C.Structure):
@@ -43,7 +44,9 @@ class Report(C.Structure):
                 ("status", C.c_void_p), ("seed_iters", C.c_int64), ("n_switches", C.c_int64),
                 ("refined", C.c_int64), ("solve_ms", C.c_double), ("block_iters", C.c_int64),
                 ("block_width", C.c_int32), ("n_blocks", C.c_int32),
-                ("kernel_ms", C.c_double * 6), ("kernel_launches", C.c_int64 * 6)]
+                ("kernel_ms", C.c_double * 6), ("kernel_launches", C.c_int64 * 6),
+                ("tile_used", C.c_int32), ("zchunk_used", C.c_int32),
+                ("shift_chunk_used", C.c_int32), ("tuned", C.c_int32), ("tune_ms", C.c_double)]
 
 KERNEL_FAMILIES = ("proj", "mu", "alpha", "update", "control", "shift")
 
@@ -81,6 +84,12 @@ def load(path: str = LIB_PATH):
     lib.scocg_destroy.restype = None
     lib.scocg_last_error.argtypes = []
     lib.scocg_last_error.restype = C.c_char_p
+    lib.scocg_struct_size.argtypes = [C.c_int32]
+    lib.scocg_struct_size.restype = C.c_int64
+    for which, mirror in enumerate((Grid, SolveOpts, Report)):
+        if lib.scocg_struct_size(which) != C.sizeof(mirror):
+            raise RuntimeError(f"{path}: {mirror.__name__} is {C.sizeof(mirror)} bytes here, "
+                               f"{lib.scocg_struct_size(which)} in the library")
     _lib = lib
     return lib
 
@@ -120,7 +129,7 @@ class Handle:
 
     def solve(self, z, rhs_idx, s_idx=None, tol=1e-10, max_iter=100000, init_seed=-1,
               seed_switch=True, full=False, refine=0, poll_every=0, use_graph=False, timing=0,
-              tile=0, zchunk=0):
+              tile=0, zchunk=0, shift_chunk=0):
         """scocg_solve; returns (rc, report dict with [K, R] arrays)."""
         lib = load()
         z = _c(z, np.complex128)
@@ -133,7 +142,7 @@ class Handle:
             nS = sp.size
         o = SolveOpts(float(tol), int(max_iter), int(init_seed), int(bool(seed_switch)),
                       int(bool(full)), int(refine), int(poll_every), int(bool(use_graph)),
-                      int(timing), int(tile), int(zchunk))
+                      int(timing), int(tile), int(zchunk), int(shift_chunk))
         iters = np.zeros((K, R), np.int64)
         est = np.zeros((K, R))
         tres = np.zeros((K, R))
@@ -151,7 +160,10 @@ class Handle:
                         refined=rep.refined, solve_ms=rep.solve_ms, block_iters=rep.block_iters,
                         block_width=rep.block_width, n_blocks=rep.n_blocks,
                         kernel_ms=dict(zip(KERNEL_FAMILIES, list(rep.kernel_ms))),
-                        kernel_launches=dict(zip(KERNEL_FAMILIES, list(rep.kernel_launches))))
+                        kernel_launches=dict(zip(KERNEL_FAMILIES, list(rep.kernel_launches))),
+                        tile=rep.tile_used, zchunk=rep.zchunk_used,
+                        shift_chunk=rep.shift_chunk_used, tuned=bool(rep.tuned),
+                        tune_ms=rep.tune_ms)
 
     def green_columns(self, out=None, dtype=C128):
         """scocg_green_columns into `out` (torch device tensor or numpy array), or a new

@@ -211,6 +211,37 @@ def test_repeatable_and_graph_replay_bitwise(dev):
     h.destroy()
 
 
+def test_autotuned_launch_shape_is_cached_and_exact(dev):
+    """SCOCG_AUTO tunes once per shape (cached in the handle), the solve with the tuned
+    shape equals an explicit solve with that shape bit for bit, and matches the default
+    shape within the parity bound."""
+    p = W.tiny_fp64()
+    h = scocg.create_from_problem(p, precision=scocg.FP64)
+    A = scocg.AUTO
+    rc, r1 = h.solve(p.z, p.rhs_idx, tol=1e-10, tile=A, zchunk=A, shift_chunk=A)
+    G1 = h.green_columns()
+    say(f"tuned: tile {r1['tile']} zchunk {r1['zchunk']} shift chunk {r1['shift_chunk']} "
+        f"in {r1['tune_ms']:.1f} ms")
+    assert rc == scocg.OK and r1["tuned"] and r1["tune_ms"] > 0
+    assert r1["tile"] in (1, 2, 3, 4) and r1["shift_chunk"] in (1, 4, 16)
+    rc, r2 = h.solve(p.z, p.rhs_idx, tol=1e-10, tile=A, zchunk=A, shift_chunk=A)
+    assert not r2["tuned"] and r2["tune_ms"] == 0
+    assert (r2["tile"], r2["zchunk"], r2["shift_chunk"]) == (r1["tile"], r1["zchunk"],
+                                                             r1["shift_chunk"])
+    assert np.array_equal(h.green_columns(), G1)
+    rc, r3 = h.solve(p.z, p.rhs_idx, tol=1e-10, tile=r1["tile"], zchunk=r1["zchunk"],
+                     shift_chunk=r1["shift_chunk"])
+    assert not r3["tuned"]
+    assert np.array_equal(h.green_columns(), G1)
+    rc, r4 = h.solve(p.z, p.rhs_idx, tol=1e-10)
+    G4 = h.green_columns()
+    with pytest.raises(scocg.ScocgError):
+        h.solve(p.z, p.rhs_idx, tol=1e-10, shift_chunk=3)
+    h.destroy()
+    eta = p.z.imag.min()
+    assert np.abs(G1 - G4).max() <= 4e-10 / eta
+
+
 def test_green_function_symmetry_and_invariants(dev):
     """S = RHS set = the whole iz=0 plane: G(z_0, z_0) is complex symmetric,
     Im G_ii < 0 and |G_ij| <= 1/eta."""

@@ -78,3 +78,14 @@ def test_solve_and_copy_reject_null_handle():
     buf = np.zeros(4)
     assert lib.scocg_green_columns(None, buf.ctypes.data, 0, 0) == scocg.EINVAL
     lib.scocg_destroy(None)
+
+
+def test_struct_sizes_match_binding():
+    """The ctypes mirrors of scocg_grid, scocg_solve_opts and scocg_report have the
+    library's sizes (load() refuses a mismatch); unknown ids give 0."""
+    import ctypes as C
+    lib = scocg.load()
+    assert lib.scocg_struct_size(0) == C.sizeof(scocg.Grid)
+    assert lib.scocg_struct_size(1) == C.sizeof(scocg.SolveOpts)
+    assert lib.scocg_struct_size(2) == C.sizeof(scocg.Report)
+    assert lib.scocg_struct_size(7) == 0
