@@ -429,3 +429,41 @@ def test_mixed_all_plane_columns_certified_by_fp64_residual(dev):
     for i, (k, j) in enumerate(pairs):
         d = np.linalg.norm(G[k, j] - ref[i])
         assert d <= (rep["true_resid"][k, j] + 1e-12) / eta, (k, j, d)
+
+
+@pytest.mark.timeout(600)
+def test_peapod_shape_sampled_pairs_full_storage(dev):
+    """The 64x64x160 peapod-shaped grid at full size (460 atoms with projectors,
+    eta = 5e-4): 8 energies spread over the window x 8 columns (4 on each boundary
+    plane), full storage.  Every pair's true residual by the oracle's operator meets
+    the tolerance; the block on the column points is complex symmetric with
+    |G| <= 1/eta and Im G_ii < 0; projected storage gives the same rows bit for bit."""
+    base = W.peapod_large()
+    R0 = base.rhs_idx.size
+    cols = np.r_[base.rhs_idx[:4], base.rhs_idx[R0 // 2:R0 // 2 + 4]]
+    ks = np.linspace(0, base.z.size - 1, 8).round().astype(int)
+    p = base.with_(z=base.z[ks], rhs_idx=cols)
+    tol = 1e-8
+    say(f"peapod shape N={p.n}, {p.n_atoms} atoms, K={p.z.size}, R={p.rhs_idx.size}")
+    h = scocg.create_from_problem(p, precision=scocg.FP64)
+    t0 = time.time()
+    # the top of the window needs about 1e5 iterations at eta = 5e-4
+    rc, rep = h.solve(p.z, p.rhs_idx, tol=tol, full=True, use_graph=True, max_iter=200000)
+    say(f"full storage: rc={rc}, {rep['seed_iters']} seed iterations, {time.time() - t0:.1f} s")
+    assert rc == scocg.OK
+    G = h.green_columns()  # [K, R, N]
+    rc2, rep2 = h.solve(p.z, p.rhs_idx, tol=tol, use_graph=True, max_iter=200000)
+    Gs = h.green_columns()  # [K, R, R] on S = the column points
+    h.destroy()
+    assert rc2 == scocg.OK
+    assert np.array_equal(Gs, G[:, :, p.rhs_idx])
+    assert np.array_equal(rep["iters"], rep2["iters"])
+    tr = true_residuals(p, G)
+    say(f"true residual (oracle operator): max {tr.max():.3e}, median {np.median(tr):.3e}")
+    assert (tr <= 1.5 * tol).all(), tr.max()
+    eta = p.z.imag.min()
+    for k in range(p.z.size):
+        g = Gs[k].T  # g[i, j] = G(S_i, rhs_j)
+        assert np.abs(g - g.T).max() <= 2 * tol / eta
+        assert (np.diag(g).imag < 0).all()
+        assert np.abs(g).max() <= 1.0 / eta
