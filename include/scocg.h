@@ -179,6 +179,37 @@ int scocg_solve(scocg_handle h, int32_t K, const double *z, int32_t R, const int
                 int32_t nS, const int64_t *s_idx, const scocg_solve_opts *opts,
                 scocg_report *rep);
 
+/* One region of a batched solve: the arguments of scocg_solve for that handle. */
+typedef struct {
+    int32_t K;              /* energies */
+    const double *z;        /* [K][2] host */
+    int32_t R;              /* right-hand sides */
+    const int64_t *rhs_idx; /* [R] host */
+    int32_t nS;             /* rows S (see scocg_solve) */
+    const int64_t *s_idx;   /* [nS] host or NULL */
+} scocg_problem;
+
+/*
+ * Batched shifted COCG over n regions (transition regions of any grid size, energy
+ * count and column count; the batched form of Sec. 3B and the Appendix): every
+ * kernel family of a seed iteration is ONE launch covering all regions (one device
+ * table of per-region arguments; regions that have finished idle at no cost), the
+ * host polls all regions together, and use_graph replays the polled iterations as
+ * one captured hipGraph.
+ *   hs        [n] distinct handles on one device and one stream, same precision and nf.
+ *   probs     [n] per-region problem (host arrays, copied during the call).
+ *   opts      common options; init_seed must be -1; SCOCG_AUTO shapes fall back to
+ *             the defaults (one launch shape serves the whole batch).
+ *   reps      [n] or NULL: per-region reports (solve_ms is the whole batch's device
+ *             time; kernel_ms/kernel_launches are the shared launches).
+ *   region_ms [n] or NULL: device ms from the start of the batch to the host poll at
+ *             which the region had finished (after its refinement, if any).
+ * Each handle's result is then read with scocg_green_columns.  Return: the worst
+ * per-region code (negative codes abort the whole batch).
+ */
+int scocg_batch_solve(int32_t n, const scocg_handle *hs, const scocg_problem *probs,
+                      const scocg_solve_opts *opts, scocg_report *reps, double *region_ms);
+
 /*
  * Copy the last solve's x^{(k)}_j[S] into dst, layout [K][R][nS] (row-major),
  * element SCOCG_C128 (2 doubles) or SCOCG_C64 (2 floats).  dst is a device
@@ -197,8 +228,8 @@ void scocg_destroy(scocg_handle h);
 const char *scocg_last_error(void);
 
 /* Size in bytes of the ABI structs, for bindings to check their mirrors:
-   which = 0 scocg_grid, 1 scocg_solve_opts, 2 scocg_report; 0 for any other
-   value.  Needs no GPU. */
+   which = 0 scocg_grid, 1 scocg_solve_opts, 2 scocg_report, 3 scocg_problem; 0 for
+   any other value.  Needs no GPU. */
 int64_t scocg_struct_size(int32_t which);
 
 #ifdef __cplusplus

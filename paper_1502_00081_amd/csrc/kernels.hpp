@@ -57,6 +57,22 @@ template <> __device__ __forceinline__ float2 from_d<float2>(double2 a) {
   return make_float2((float)a.x, (float)a.y);
 }
 
+// Pointers held in argument tables (device memory, read by every workgroup of a
+// batched launch) are typed global in device code, so the compiler emits global
+// rather than flat memory instructions through them; the host sees plain pointers
+// of the same size.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define SCOCG_GLOBAL __attribute__((address_space(1)))
+#else
+#define SCOCG_GLOBAL
+#endif
+template <typename U>
+using gptr = SCOCG_GLOBAL U*;
+template <typename U>
+__host__ __device__ inline gptr<U> to_g(U* p) {
+  return (gptr<U>)p;
+}
+
 // ------------------------------------------------------------------ state records
 struct ColState {
   double2 rho;         // (r_n, r_n) of the current seed (unscaled true value)
@@ -116,37 +132,39 @@ struct StencilGrid {
 template <typename T>
 struct ProjArgs {
   using cT = typename cplx_of<T>::type;
-  const int32_t* aptr;   // [n_atoms+1] atom-major CSR
-  const int32_t* aidx;   // [E] grid index
-  const T* aval;         // [E][4]
-  const T* aD;           // [n_atoms][4]
+  gptr<const int32_t> aptr;   // [n_atoms+1] atom-major CSR
+  gptr<const int32_t> aidx;   // [E] grid index
+  gptr<const T> aval;         // [E][4]
+  gptr<const T> aD;           // [n_atoms][4]
   int n_proj, n_atoms;
-  cT* dc;                // out [nb][n_atoms][4][B]: D_l C_l
-  double2* qa;           // out [nb][n_atoms][B]: sum_l C_l D_l C_l (null: not needed)
+  gptr<cT> dc;                // out [nb][n_atoms][4][B]: D_l C_l
+  gptr<double2> qa;           // out [nb][n_atoms][B]: sum_l C_l D_l C_l (null: not needed)
 };
 
 template <typename T>
 struct StencilArgs {
   using cT = typename cplx_of<T>::type;
-  const cT* r;           // [nb][nz+2NF][nxy][B] stored r_n, from the first padding plane
-  cT* io;                // same layout; UPDATE: r_{n-1} in, r_{n+1} out; APPLY: H r out
+  gptr<const cT> r;           // [nb][nz+2NF][nxy][B] stored r_n, from the first padding plane
+  gptr<cT> io;                // same layout; UPDATE: r_{n-1} in, r_{n+1} out; APPLY: H r out
+  gptr<cT> bufs[2];           // pingpong: r = bufs[cur], io = bufs[cur ^ 1] (r, io unused)
+  int pingpong;
   int64_t bstride;       // elements per column block ((nz+2NF)*nxy*B)
-  const T* vloc;         // [N]
+  gptr<const T> vloc;         // [N]
   Coefs<T> co;
   int nx, ny, nz, nxy;
   int ntx, nty;          // x-y tiles per plane
   int zc, nzc;           // planes per workgroup, z-chunks per plane column
   int nb;                // column blocks in the launch
   int nper;              // workgroups per XCD slice of the launch (grid = 8 * nper)
-  const int32_t* prow;   // [N+1] point -> projector entries (null if no atoms)
-  const int32_t* patom;  // [E] atom of each entry
-  const T* pval;         // [E][4] projector values
-  const cT* dc;          // [nb][n_atoms][4][B] D_a P_a^T r
+  gptr<const int32_t> prow;   // [N+1] point -> projector entries (null if no atoms)
+  gptr<const int32_t> patom;  // [E] atom of each entry
+  gptr<const T> pval;         // [E][4] projector values
+  gptr<const cT> dc;          // [nb][n_atoms][4][B] D_a P_a^T r
   int n_atoms;
-  const ColState* cols;  // [nb*B]
-  const int32_t* blk_active;  // [nb] (null: all active)
-  double2* part0;        // [nb][nwg][B] mu or rho partials, nwg = nzc*ntx*nty
-  double* part1;         // [nb][nwg][B] ||r||^2 partials (UPDATE)
+  gptr<const ColState> cols;  // [nb*B]
+  gptr<const int32_t> blk_active;  // [nb] (null: all active)
+  gptr<double2> part0;        // [nb][nwg][B] mu or rho partials, nwg = nzc*ntx*nty
+  gptr<double> part1;         // [nb][nwg][B] ||r||^2 partials (UPDATE)
   int nproj_wg;          // MU: leading workgroups doing the projector contraction
   ProjArgs<T> proj;
 };
@@ -176,6 +194,18 @@ __device__ __forceinline__ V ld_or_zero(const V* p, bool ok) {
 __device__ __forceinline__ int wrapi(int v, int n) {
   v %= n;
   return v < 0 ? v + n : v;
+}
+
+// Batched launches: workgroups [off[r], off[r+1]) of a launch serve region r
+// (off[0] = 0, ascending, off[nreg] = grid).  Returns r for workgroup b.
+__device__ __forceinline__ int region_of(const int32_t* __restrict__ off, int nreg, int b) {
+  int lo = 0, hi = nreg - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
 }
 
 // ------------------------------------------------------------------ projector contraction
@@ -301,6 +331,8 @@ struct StencilWG {
   static constexpr uint32_t ESZ = sizeof(cT);
 
   const StencilArgs<T>& a;
+  const cT* rsrc;  // r_n (padded, block 0)
+  cT* iodst;       // UPDATE/APPLY output (padded, block 0)
   char* smem;
   int c, cb, z0, z1, nxy;
   const char* rbase;  // uniform: this block's vector, first padding plane
@@ -315,7 +347,8 @@ struct StencilWG {
   double2 acc0;
   double acc1;
 
-  __device__ __forceinline__ StencilWG(const StencilArgs<T>& args, char* sm) : a(args), smem(sm) {}
+  __device__ __forceinline__ StencilWG(const StencilArgs<T>& args, const cT* r, cT* io, char* sm)
+      : a(args), rsrc(r), iodst(io), smem(sm) {}
 
   __device__ __forceinline__ const cT& ldr(uint32_t plane_pad, uint32_t lane_off) const {
     return *reinterpret_cast<const cT*>(rbase + plane_pad * pstride + lane_off);
@@ -336,8 +369,8 @@ struct StencilWG {
     nxy = a.nxy;
     const int nx = a.nx, ny = a.ny;
     pstride = (uint32_t)nxy * B * ESZ;
-    rbase = reinterpret_cast<const char*>(a.r + (int64_t)cb * a.bstride);
-    iobase = (MODE == MODE_MU) ? nullptr : reinterpret_cast<char*>(a.io + (int64_t)cb * a.bstride);
+    rbase = reinterpret_cast<const char*>(rsrc + (int64_t)cb * a.bstride);
+    iobase = (MODE == MODE_MU) ? nullptr : reinterpret_cast<char*>(iodst + (int64_t)cb * a.bstride);
 #pragma unroll
     for (int m = 0; m < OPT; ++m) {
       const int pi = pl + m * PL;
@@ -603,11 +636,21 @@ struct StencilWG {
 // (atom, column block).
 template <typename T, int NF, int B, int MODE, int TX, int TY, int NT, bool FULL>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4)))
-void k_stencil(StencilArgs<T> a) {
+void k_stencil(const StencilArgs<T>* __restrict__ regs, const int32_t* __restrict__ off,
+               int nreg, int cur) {
   using SW = StencilWG<T, NF, B, MODE, TX, TY, NT, FULL>;
+  using cT = typename cplx_of<T>::type;
   constexpr int PROJ_BYTES = 8 * NT * (int)sizeof(T);
   __shared__ __align__(16) char smem[SW::SMEM > PROJ_BYTES ? SW::SMEM : PROJ_BYTES];
   int bid = blockIdx.x;
+  const int rg = region_of(off, nreg, bid);
+  // a private copy: the compiler keeps the uniform fields in scalar registers instead
+  // of reloading them from the table after every global store
+  const StencilArgs<T> a = regs[rg];
+  bid -= off[rg];
+  // (selects, not a dynamic index: the copy of the table entry must stay in registers)
+  const cT* rsrc = a.pingpong ? (cur ? a.bufs[1] : a.bufs[0]) : a.r;
+  cT* iodst = a.pingpong ? (cur ? a.bufs[0] : a.bufs[1]) : a.io;
   if (MODE == MODE_MU && a.nproj_wg > 0) {
     if (bid < a.nproj_wg) {
       const int na = a.proj.n_atoms;
@@ -615,7 +658,7 @@ void k_stencil(StencilArgs<T> a) {
       const int at = bid % na, cb = bid / na;
       if (a.blk_active && !a.blk_active[cb]) return;
       // plane-0 view of the padded vector
-      proj_contract<T, B, NT>(a.r + (int64_t)NF * a.nxy * B, a.bstride, a.proj, at, cb, smem);
+      proj_contract<T, B, NT>(rsrc + (int64_t)NF * a.nxy * B, a.bstride, a.proj, at, cb, smem);
       return;
     }
     bid -= a.nproj_wg;
@@ -625,7 +668,7 @@ void k_stencil(StencilArgs<T> a) {
   const int total = a.nb * a.nzc * ntile;
   const int lid = (bid % 8) * a.nper + bid / 8;
   if (lid >= total) return;
-  SW w(a, smem);
+  SW w(a, rsrc, iodst, smem);
   if (!w.setup(lid)) return;
   w.march();
   if (MODE == MODE_APPLY) return;
@@ -636,13 +679,29 @@ void k_stencil(StencilArgs<T> a) {
 // One workgroup per column block: fixed-order reduction of the mu partials, then
 //   alpha_n = rho_n / (mu_n - beta_{n-1}/alpha_{n-1} rho_n),  c_n = beta_{n-1} alpha_n / alpha_{n-1}
 // and the coefficients of the UPDATE pass in stored-buffer units.
+struct AlphaArgs {
+  gptr<const double2> part;        // [nb][nwg][B] mu partials
+  int nwg;
+  gptr<const double2> qa;          // [nb][n_atoms][B] projector shares
+  int n_atoms;
+  gptr<ColState> cols;             // [nb*B]
+  gptr<const int32_t> blk_active;  // [nb]
+};
+
+// one workgroup per column block of every region (off: blocks per region)
 template <int B>
-__global__ __launch_bounds__(WG) void k_alpha(const double2* __restrict__ part, int nwg,
-                                               const double2* __restrict__ qa, int n_atoms,
-                                               ColState* __restrict__ cols, int buf_cur,
-                                               const int32_t* __restrict__ blk_active) {
+__global__ __launch_bounds__(WG) void k_alpha(const AlphaArgs* __restrict__ regs,
+                                               const int32_t* __restrict__ off, int nreg,
+                                               int buf_cur) {
   constexpr int PTS = WG / B;
-  const int tid = threadIdx.x, c = tid % B, ln = tid / B, cb = blockIdx.x;
+  const int rg = region_of(off, nreg, blockIdx.x);
+  const AlphaArgs ar = regs[rg];
+  const auto part = ar.part;
+  const auto qa = ar.qa;
+  const int nwg = ar.nwg, n_atoms = ar.n_atoms;
+  const auto cols = ar.cols;
+  const auto blk_active = ar.blk_active;
+  const int tid = threadIdx.x, c = tid % B, ln = tid / B, cb = blockIdx.x - off[rg];
   if (!blk_active[cb]) return;
   // mu^st = sum of the local stencil partials - sum over atoms of r^T P D P^T r
   double2 acc = mk(0, 0);
@@ -683,21 +742,20 @@ __global__ __launch_bounds__(WG) void k_alpha(const double2* __restrict__ part, 
 
 // ------------------------------------------------------------------ column control
 struct ControlArgs {
-  const double2* part_rho;  // [nb][nwg][B]
-  const double* part_nu;    // [nb][nwg][B]
+  gptr<const double2> part_rho;  // [nb][nwg][B]
+  gptr<const double> part_nu;    // [nb][nwg][B]
   int nwg;
-  ColState* cols;
-  ShiftState* sh;           // [nb][K][B]
-  ShiftCoef* coef;          // [nb][K][B]
-  const double2* z;         // [nb][K][B] energies per column
+  gptr<ColState> cols;
+  gptr<ShiftState> sh;           // [nb][K][B]
+  gptr<ShiftCoef> coef;          // [nb][K][B]
+  gptr<const double2> z;         // [nb][K][B] energies per column
   int K;
-  int32_t* list;            // [2][nb][K]
-  int32_t* cnt;             // [2][nb]
-  int32_t* k5cnt;           // [nb] entries for k_shift this iteration
-  int32_t* blk_active;      // [nb]
-  int32_t* blk_iter;        // [nb]
-  int par;                  // list parity of this iteration (reads list[par], writes list[par^1])
-  int buf_new;              // Krylov buffer holding r_{n+1}
+  gptr<int32_t> list;            // [2][nb][K]
+  gptr<int32_t> cnt;             // [2][nb]
+  gptr<int32_t> k5cnt;           // [nb] entries for k_shift this iteration
+  gptr<int32_t> blk_active;      // [nb]
+  gptr<int32_t> blk_iter;        // [nb]
+  int nb;                   // column blocks
   double tol;
   int64_t max_iter;
   int seed_switch;
@@ -720,10 +778,15 @@ struct ControlArgs {
 constexpr int CT = 512;  // threads of the control kernel
 
 template <int B>
-__global__ __launch_bounds__(CT) void k_control(ControlArgs a) {
+__global__ __launch_bounds__(CT) void k_control(const ControlArgs* __restrict__ regs,
+                                                 const int32_t* __restrict__ off, int nreg,
+                                                 int par) {
   constexpr int PL = CT / B;
   constexpr int NWAVE = CT / 64;
-  const int tid = threadIdx.x, c = tid % B, ln = tid / B, cb = blockIdx.x;
+  const int rg = region_of(off, nreg, blockIdx.x);
+  const ControlArgs a = regs[rg];
+  const int buf_new = par ^ 1;  // Krylov buffer holding r_{n+1}
+  const int tid = threadIdx.x, c = tid % B, ln = tid / B, cb = blockIdx.x - off[rg];
   if (!a.blk_active[cb]) {
     if (tid == 0) a.k5cnt[cb] = 0;
     return;
@@ -765,7 +828,7 @@ __global__ __launch_bounds__(CT) void k_control(ControlArgs a) {
   }
   if (tid < B) {
     ColState& cs = a.cols[cb * B + tid];
-    cs.scale[a.buf_new] = mk(1.0, 0.0);  // r_{n+1} was just written unscaled
+    cs.scale[buf_new] = mk(1.0, 0.0);  // r_{n+1} was just written unscaled
     const int live = !cs.done && !cs.breakdown;
     s_live[tid] = live;
     s_rhon[tid] = sh_rho[tid];
@@ -782,10 +845,9 @@ __global__ __launch_bounds__(CT) void k_control(ControlArgs a) {
   __syncthreads();
 
   // 2. per (active shift, column): pi recurrence, shift coefficients, convergence
-  const int par = a.par;
-  const int32_t* lcur = a.list + ((int64_t)par * gridDim.x + cb) * K;
-  int32_t* lnext = a.list + ((int64_t)(par ^ 1) * gridDim.x + cb) * K;
-  const int ncur = a.cnt[par * gridDim.x + cb];
+  const int32_t* lcur = a.list + ((int64_t)par * a.nb + cb) * K;
+  int32_t* lnext = a.list + ((int64_t)(par ^ 1) * a.nb + cb) * K;
+  const int ncur = a.cnt[par * a.nb + cb];
   const bool live_c = s_live[c];
   const bool brk_c = a.cols[cb * B + c].breakdown;
   for (int e = ln; e < ncur; e += PL) {
@@ -934,8 +996,8 @@ __global__ __launch_bounds__(CT) void k_control(ControlArgs a) {
         alpha = cmul(qq, alpha);                   // alpha^{(s~)}_n
         beta = cmul(cmul(qq, qq), beta);           // beta^{(s~)}_n
         rho_new = cdiv(rho_new, cmul(fn, fn));     // (r~_{n+1}, r~_{n+1})
-        cs.scale[a.buf_new] = cdiv(cs.scale[a.buf_new], fn);
-        cs.scale[a.buf_new ^ 1] = cdiv(cs.scale[a.buf_new ^ 1], fc);
+        cs.scale[buf_new] = cdiv(cs.scale[buf_new], fn);
+        cs.scale[buf_new ^ 1] = cdiv(cs.scale[buf_new ^ 1], fc);
         cs.zs = a.z[((int64_t)cb * K + sw) * B + tid];
         cs.seed = sw;
         cs.nswitch += 1;
@@ -977,7 +1039,7 @@ __global__ __launch_bounds__(CT) void k_control(ControlArgs a) {
     a.blk_active[cb] = any;
     a.blk_iter[cb] = n + 1;
     a.k5cnt[cb] = ncur;
-    a.cnt[(par ^ 1) * gridDim.x + cb] = any ? nnext : 0;
+    a.cnt[(par ^ 1) * a.nb + cb] = any ? nnext : 0;
   }
 }
 
@@ -985,30 +1047,51 @@ __global__ __launch_bounds__(CT) void k_control(ControlArgs a) {
 //   x^(k) += alpha^(k)_n p^(k);   p^(k) = r_{n+1}[S] / pi_{n+1} + beta^(k)_n p^(k)
 // grid: (ceil(nS*B/WG), ceil(K/KCH), nb); each thread owns one (row of S, column)
 // and walks a chunk of the block's active shift list.
-template <typename T, int B, int KCH>
-__global__ __launch_bounds__(WG) void k_shift(const typename cplx_of<T>::type* __restrict__ rnew,
-                                               int64_t bstride, const int32_t* __restrict__ srow,
-                                               int nS, const int32_t* __restrict__ list,
-                                               const int32_t* __restrict__ k5cnt, int K,
-                                               const ShiftCoef* __restrict__ coef,
-                                               double2* __restrict__ x,
-                                               typename cplx_of<T>::type* __restrict__ p) {
+template <typename T>
+struct ShiftArgs {
   using cT = typename cplx_of<T>::type;
-  const int cb = blockIdx.z;
-  const int cnt = k5cnt[cb];
-  const int e0 = blockIdx.y * KCH;
+  gptr<const cT> rnew[2];          // plane 0 of the Krylov buffers; r_{n+1} is rnew[par ^ 1]
+  int64_t bstride;            // elements per column block
+  gptr<const int32_t> srow;        // [nS] rows S (null: all N rows)
+  int nS;
+  gptr<const int32_t> list;        // [2][nb][K] active shift lists (read list[par])
+  gptr<const int32_t> k5cnt;       // [nb] entries of the list this iteration
+  int K, nb;
+  gptr<const ShiftCoef> coef;      // [nb][K][B]
+  gptr<double2> x;                 // [nb][K][nS][B]
+  gptr<cT> p;                      // [nb][K][nS][B]
+  int gx, gy;                 // workgroups per block along rows and along the list
+};
+
+// x^(k) += alpha^(k) p^(k);  p^(k) = r_{n+1}[S] / pi^(k)_{n+1} + beta^(k) p^(k)  (Eqs. A11-A12):
+// per region gx * gy * nb workgroups: WG rows of S x KCH list entries x column block.
+template <typename T, int B, int KCH>
+__global__ __launch_bounds__(WG) void k_shift(const ShiftArgs<T>* __restrict__ regs,
+                                               const int32_t* __restrict__ off, int nreg,
+                                               int par) {
+  using cT = typename cplx_of<T>::type;
+  const int rg = region_of(off, nreg, blockIdx.x);
+  const ShiftArgs<T> a = regs[rg];
+  const int lb = blockIdx.x - off[rg];
+  const int bx = lb % a.gx, by = (lb / a.gx) % a.gy, cb = lb / (a.gx * a.gy);
+  const int cnt = a.k5cnt[cb];
+  const int e0 = by * KCH;
   if (e0 >= cnt) return;
   const int e1 = min(e0 + KCH, cnt);
-  const int64_t gid = (int64_t)blockIdx.x * WG + threadIdx.x;
+  const int nS = a.nS, K = a.K;
+  const int64_t gid = (int64_t)bx * WG + threadIdx.x;
   if (gid >= (int64_t)nS * B) return;
   const int i = (int)(gid / B), c = (int)(gid % B);
-  const int64_t row = srow ? (int64_t)srow[i] : (int64_t)i;
-  const double2 rv = to_d(rnew[(int64_t)cb * bstride + row * B + c]);
-  const int32_t* l = list + (int64_t)cb * K;
+  const int64_t row = a.srow ? (int64_t)a.srow[i] : (int64_t)i;
+  const cT* rnew = par ? a.rnew[0] : a.rnew[1];  // r_{n+1}: buffer par ^ 1
+  const double2 rv = to_d(rnew[(int64_t)cb * a.bstride + row * B + c]);
+  const int32_t* l = a.list + ((int64_t)par * a.nb + cb) * K;
+  double2* __restrict__ x = a.x;
+  cT* __restrict__ p = a.p;
   for (int e = e0; e < e1; ++e) {
     const int k = l[e];
     const int64_t so = ((int64_t)cb * K + k) * B + c;
-    const ShiftCoef cf = coef[so];
+    const ShiftCoef cf = a.coef[so];
     if (!cf.upd) continue;
     const int64_t vo = (((int64_t)cb * K + k) * nS + i) * B + c;
     const double2 xv = x[vo];

@@ -291,80 +291,110 @@ struct Solver {
     return g;
   }
 
-  template <int MODE, int NF, int TX, int TY, int NT>
-  void launch_v(const StencilArgs<T>& a, int grid) {
-    // interior tiles only when the tile divides the plane
-    if (h.nx % TX == 0 && h.ny % TY == 0 && NF == 4)
-      hipLaunchKernelGGL((k_stencil<T, NF, B, MODE, TX, TY, NT, true>), dim3(grid + a.nproj_wg),
-                         dim3(NT), 0, h.stream, a);
-    else
-      hipLaunchKernelGGL((k_stencil<T, NF, B, MODE, TX, TY, NT, false>), dim3(grid + a.nproj_wg),
-                         dim3(NT), 0, h.stream, a);
+  // interior-only tiles (the FULL kernels) when the tile divides the plane
+  bool full_tiles(int variant) const {
+    const TileCfg tc = tile_cfg(h.nf == 4 ? variant : 1);
+    return h.nf == 4 && h.nx % tc.tx == 0 && h.ny % tc.ty == 0;
   }
 
-  // MODE_MU with qa != null also contracts the projectors (into dc and qa)
-  template <int MODE>
-  void launch_stencil(const cT* r, cT* io, const ColState* cols, const int32_t* blk_active,
-                      int nb, const StencilGrid& g, double2* part0, double* part1, cT* dc,
-                      double2* qa = nullptr) {
+  // One region's arguments of a stencil pass.  MODE_MU with qa != null also contracts
+  // the projectors (into dc and qa) in nproj_wg leading workgroups.  r/io (or the
+  // ping-pong pair) are filled by the caller.
+  StencilArgs<T> stencil_args(int mode, const StencilGrid& g, int nb, const ColState* cols,
+                              const int32_t* blk_active, double2* part0, double* part1, cT* dc,
+                              double2* qa) const {
     StencilArgs<T> a{};
     a.bstride = bstride();
-    if (MODE == MODE_MU && qa && h.n_atoms) {
+    if (mode == MODE_MU && qa && h.n_atoms) {
       a.nproj_wg = (h.n_atoms * nb + 7) / 8 * 8;
       a.proj = proj_args(dc, qa);
     }
-    a.r = r;
-    a.io = io;
-    a.vloc = op_vloc();
+    a.vloc = to_g(op_vloc());
     a.co = make_coefs<T>(h);
     a.nx = h.nx; a.ny = h.ny; a.nz = h.nz; a.nxy = h.nxy;
     a.ntx = g.ntx; a.nty = g.nty;
     a.zc = g.zc; a.nzc = g.nzc;
     a.nb = nb;
     a.nper = g.nper;
-    a.prow = h.n_atoms ? h.prow.as<int32_t>() : nullptr;
-    a.patom = h.patom.as<int32_t>();
-    a.pval = op_pval();
-    a.dc = dc;
+    a.prow = h.n_atoms ? to_g(h.prow.as<int32_t>()) : nullptr;
+    a.patom = to_g(h.patom.as<int32_t>());
+    a.pval = to_g(op_pval());
+    a.dc = to_g(dc);
     a.n_atoms = h.n_atoms;
-    a.cols = cols;
-    a.blk_active = blk_active;
-    a.part0 = part0;
-    a.part1 = part1;
-    switch (h.nf) {
-      case 1: launch_v<MODE, 1, 16, 8, 1024>(a, g.grid); break;
-      case 2: launch_v<MODE, 2, 16, 8, 1024>(a, g.grid); break;
-      case 3: launch_v<MODE, 3, 16, 8, 1024>(a, g.grid); break;
+    a.cols = to_g(cols);
+    a.blk_active = to_g(blk_active);
+    a.part0 = to_g(part0);
+    a.part1 = to_g(part1);
+    return a;
+  }
+
+  // workgroups of one region in a stencil launch
+  static int stencil_wgs(const StencilArgs<T>& a, const StencilGrid& g) { return g.grid + a.nproj_wg; }
+
+  template <int MODE, int NF, int TX, int TY, int NT>
+  static void launch_v(hipStream_t st, bool full, const StencilArgs<T>* regs, const int32_t* off,
+                       int nreg, int grid, int cur) {
+    if (full && NF == 4)
+      hipLaunchKernelGGL((k_stencil<T, NF, B, MODE, TX, TY, NT, true>), dim3(grid), dim3(NT), 0,
+                         st, regs, off, nreg, cur);
+    else
+      hipLaunchKernelGGL((k_stencil<T, NF, B, MODE, TX, TY, NT, false>), dim3(grid), dim3(NT), 0,
+                         st, regs, off, nreg, cur);
+  }
+
+  // one stencil launch over a device table of nreg regions (common nf, tile variant)
+  template <int MODE>
+  static void launch_table(hipStream_t st, int nf, int variant, bool full,
+                           const StencilArgs<T>* regs, const int32_t* off, int nreg, int grid,
+                           int cur) {
+    switch (nf) {
+      case 1: launch_v<MODE, 1, 16, 8, 1024>(st, full, regs, off, nreg, grid, cur); break;
+      case 2: launch_v<MODE, 2, 16, 8, 1024>(st, full, regs, off, nreg, grid, cur); break;
+      case 3: launch_v<MODE, 3, 16, 8, 1024>(st, full, regs, off, nreg, grid, cur); break;
       default:
         if constexpr (B == 8) {
-          switch (g.variant) {
-            case 2: launch_v<MODE, 4, 16, 4, 512>(a, g.grid); break;
-            case 3: launch_v<MODE, 4, 8, 8, 512>(a, g.grid); break;
-            case 4: launch_v<MODE, 4, 16, 8, 512>(a, g.grid); break;
-            default: launch_v<MODE, 4, 16, 8, 1024>(a, g.grid); break;
+          switch (variant) {
+            case 2: launch_v<MODE, 4, 16, 4, 512>(st, full, regs, off, nreg, grid, cur); break;
+            case 3: launch_v<MODE, 4, 8, 8, 512>(st, full, regs, off, nreg, grid, cur); break;
+            case 4: launch_v<MODE, 4, 16, 8, 512>(st, full, regs, off, nreg, grid, cur); break;
+            default: launch_v<MODE, 4, 16, 8, 1024>(st, full, regs, off, nreg, grid, cur); break;
           }
         } else {
-          switch (g.variant) {
-            case 2: launch_v<MODE, 4, 16, 4, 512>(a, g.grid); break;
-            case 3: launch_v<MODE, 4, 8, 8, 1024>(a, g.grid); break;
-            case 4: launch_v<MODE, 4, 8, 8, 512>(a, g.grid); break;
-            default: launch_v<MODE, 4, 16, 8, 1024>(a, g.grid); break;
+          switch (variant) {
+            case 2: launch_v<MODE, 4, 16, 4, 512>(st, full, regs, off, nreg, grid, cur); break;
+            case 3: launch_v<MODE, 4, 8, 8, 1024>(st, full, regs, off, nreg, grid, cur); break;
+            case 4: launch_v<MODE, 4, 8, 8, 512>(st, full, regs, off, nreg, grid, cur); break;
+            default: launch_v<MODE, 4, 16, 8, 1024>(st, full, regs, off, nreg, grid, cur); break;
           }
         }
     }
     KCHK();
   }
 
+  // a one-off single-region stencil pass (operator apply): uploads a one-entry table
+  template <int MODE>
+  void launch_stencil_once(const cT* r, cT* io, int nb, const StencilGrid& g, cT* dc) {
+    StencilArgs<T> a = stencil_args(MODE, g, nb, nullptr, nullptr, nullptr, nullptr, dc, nullptr);
+    a.r = to_g(r);
+    a.io = to_g(io);
+    DevBuf tab, off;
+    upload(tab, std::vector<StencilArgs<T>>{a}, h.stream);
+    upload(off, std::vector<int32_t>{0, stencil_wgs(a, g)}, h.stream);
+    launch_table<MODE>(h.stream, h.nf, g.variant, full_tiles(g.variant), tab.as<StencilArgs<T>>(),
+                       off.as<int32_t>(), 1, stencil_wgs(a, g), 0);
+    HIPCHK(hipStreamSynchronize(h.stream));  // tab, off are freed on return
+  }
+
   ProjArgs<T> proj_args(cT* dc, double2* qa) const {
     ProjArgs<T> pa{};
-    pa.aptr = h.aptr.as<int32_t>();
-    pa.aidx = h.aidx.as<int32_t>();
-    pa.aval = op_aval();
-    pa.aD = op_aD();
+    pa.aptr = to_g(h.aptr.as<int32_t>());
+    pa.aidx = to_g(h.aidx.as<int32_t>());
+    pa.aval = to_g(op_aval());
+    pa.aD = to_g(op_aD());
     pa.n_proj = h.n_proj;
     pa.n_atoms = h.n_atoms;
-    pa.dc = dc;
-    pa.qa = qa;
+    pa.dc = to_g(dc);
+    pa.qa = to_g(qa);
     return pa;
   }
 
@@ -379,77 +409,6 @@ struct Solver {
   // dynamic LDS of k_control: |pi| (double) and an activity byte per (shift, column)
   static size_t control_lds(int K) { return (size_t)K * B * (sizeof(double) + 1); }
 
-  // ev: null, or 2*SCOCG_K_FAMILIES events recorded around the launches of this iteration
-  // timing mode 1 records every family, mode 2 only the r_{n+1} pass
-  int timing_mode = 0;
-  void mark(hipEvent_t* ev, int fam, int end) {
-    if (!ev || (timing_mode == 2 && fam != SCOCG_K_UPDATE)) return;
-    HIPCHK(hipEventRecord(ev[2 * fam + end], h.stream));
-  }
-
-  // x^(k), p^(k) update, KCH energies per workgroup
-  template <int KCH>
-  void launch_shift(cT* rn, int par) {
-    const int64_t rows = (int64_t)S.nS * B;
-    dim3 g5(nblocks(rows, WG), nblocks(S.K, KCH), S.nb);
-    hipLaunchKernelGGL((k_shift<T, B, KCH>), g5, dim3(WG), 0, h.stream, plane0(rn), bstride(),
-                       S.full ? nullptr : S.srow.as<int32_t>(), S.nS,
-                       S.list.as<int32_t>() + (int64_t)par * S.nb * S.K, S.k5cnt.as<int32_t>(),
-                       S.K, S.coef.as<ShiftCoef>(), S.x.as<double2>(), S.p.as<cT>());
-    KCHK();
-  }
-
-  void one_iteration(int cur, int par, const scocg_solve_opts& o, hipEvent_t* ev) {
-    cT* rc = (cur ? S.r1 : S.r0).template as<cT>();
-    cT* rn = (cur ? S.r0 : S.r1).template as<cT>();
-    const int32_t* act = S.blk_active.as<int32_t>();
-    mark(ev, SCOCG_K_MU, 0);
-    launch_stencil<MODE_MU>(rc, nullptr, S.cols.as<ColState>(), act, S.nb, S.g,
-                            S.part0.as<double2>(), nullptr, S.dc.as<cT>(), S.qa.as<double2>());
-    mark(ev, SCOCG_K_MU, 1);
-    mark(ev, SCOCG_K_ALPHA, 0);
-    hipLaunchKernelGGL((k_alpha<B>), dim3(S.nb), dim3(WG), 0, h.stream, S.part0.as<double2>(),
-                       S.nwg, S.qa.as<double2>(), h.n_atoms, S.cols.as<ColState>(), cur, act);
-    KCHK();
-    mark(ev, SCOCG_K_ALPHA, 1);
-    mark(ev, SCOCG_K_UPDATE, 0);
-    launch_stencil<MODE_UPDATE>(rc, rn, S.cols.as<ColState>(), act, S.nb, S.g,
-                                S.part0.as<double2>(), S.part1.as<double>(), S.dc.as<cT>());
-    mark(ev, SCOCG_K_UPDATE, 1);
-    ControlArgs ca{};
-    ca.part_rho = S.part0.as<double2>();
-    ca.part_nu = S.part1.as<double>();
-    ca.nwg = S.nwg;
-    ca.cols = S.cols.as<ColState>();
-    ca.sh = S.sh.as<ShiftState>();
-    ca.coef = S.coef.as<ShiftCoef>();
-    ca.z = S.z.as<double2>();
-    ca.K = S.K;
-    ca.list = S.list.as<int32_t>();
-    ca.cnt = S.cnt.as<int32_t>();
-    ca.k5cnt = S.k5cnt.as<int32_t>();
-    ca.blk_active = S.blk_active.as<int32_t>();
-    ca.blk_iter = S.blk_iter.as<int32_t>();
-    ca.par = par;
-    ca.buf_new = cur ^ 1;
-    ca.tol = o.tol;
-    ca.max_iter = o.max_iter;
-    ca.seed_switch = o.seed_switch;
-    ca.stall = DBL ? 0 : kStallWindow;
-    ca.floor_est = DBL ? 0.0 : kMixedFloor;
-    mark(ev, SCOCG_K_CONTROL, 0);
-    hipLaunchKernelGGL((k_control<B>), dim3(S.nb), dim3(CT), control_lds(S.K), h.stream, ca);
-    KCHK();
-    mark(ev, SCOCG_K_CONTROL, 1);
-    mark(ev, SCOCG_K_SHIFT, 0);
-    switch (S.kch) {
-      case 1: launch_shift<1>(rn, par); break;
-      case 16: launch_shift<16>(rn, par); break;
-      default: launch_shift<4>(rn, par); break;
-    }
-    mark(ev, SCOCG_K_SHIFT, 1);
-  }
-
   // FP64 operator data (the handle's own arrays for SCOCG_FP64, the FP64 copies otherwise)
   const double* vloc64() const {
     return h.precision == SCOCG_FP64 ? h.vloc.as<double>() : h.vloc64.as<double>();
@@ -457,13 +416,13 @@ struct Solver {
   ProjArgs<double> proj64(double2* dc) const {
     const bool f = h.precision == SCOCG_FP64;
     ProjArgs<double> pa{};
-    pa.aptr = h.aptr.as<int32_t>();
-    pa.aidx = h.aidx.as<int32_t>();
-    pa.aval = f ? h.aval.as<double>() : h.aval64.as<double>();
-    pa.aD = f ? h.aD.as<double>() : h.aD64.as<double>();
+    pa.aptr = to_g(h.aptr.as<int32_t>());
+    pa.aidx = to_g(h.aidx.as<int32_t>());
+    pa.aval = to_g(f ? h.aval.as<double>() : h.aval64.as<double>());
+    pa.aD = to_g(f ? h.aD.as<double>() : h.aD64.as<double>());
     pa.n_proj = h.n_proj;
     pa.n_atoms = h.n_atoms;
-    pa.dc = dc;
+    pa.dc = to_g(dc);
     pa.qa = nullptr;
     return pa;
   }
@@ -609,63 +568,8 @@ struct Solver {
     HIPCHK(hipStreamSynchronize(st));  // prho, pnu are freed on return
   }
 
-  // the seed iterations, polling the block flags every `poll` iterations
-  int64_t iterate(const scocg_solve_opts& o, double* kms, int64_t* kcount) {
-    hipStream_t st = h.stream;
-    const int nb = S.nb;
-    int poll = o.poll_every > 0 ? o.poll_every : 16;
-    if (poll & 1) ++poll;  // even: the buffer and list parities return to 0 after each poll
-    int64_t it = 0;
-    hipGraphExec_t gexec = nullptr;
-    hipGraph_t graph = nullptr;
-    // timing: one event pair per kernel family per iteration of a poll chunk
-    timing_mode = o.timing;
-    std::vector<hipEvent_t> evs;
-    if (o.timing) {
-      evs.resize((size_t)poll * 2 * SCOCG_K_FAMILIES);
-      for (auto& e : evs) HIPCHK(hipEventCreate(&e));
-    }
-    auto ev_of = [&](int s2) { return o.timing ? &evs[(size_t)s2 * 2 * SCOCG_K_FAMILIES] : nullptr; };
-    // events recorded during capture cannot be read back after a replay on this
-    // runtime: timing runs use direct launches
-    const bool use_graph = o.use_graph && !o.timing;
-    while (true) {
-      if (use_graph) {
-        if (!gexec) {
-          HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-          for (int s2 = 0; s2 < poll; ++s2) one_iteration(s2 & 1, s2 & 1, o, ev_of(s2));
-          HIPCHK(hipStreamEndCapture(st, &graph));
-          HIPCHK(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
-        }
-        HIPCHK(hipGraphLaunch(gexec, st));
-      } else {
-        for (int s2 = 0; s2 < poll; ++s2) one_iteration(s2 & 1, s2 & 1, o, ev_of(s2));
-      }
-      it += poll;
-      HIPCHK(hipMemcpyAsync(S.h_flags, S.blk_active.p, nb * sizeof(int32_t),
-                            hipMemcpyDeviceToHost, st));
-      HIPCHK(hipStreamSynchronize(st));
-      if (o.timing) {
-        for (int s2 = 0; s2 < poll; ++s2)
-          for (int f = 0; f < SCOCG_K_FAMILIES; ++f) {
-            if (f == SCOCG_K_PROJ) continue;  // fused into the MU launch
-            if (o.timing == 2 && f != SCOCG_K_UPDATE) continue;
-            float t = 0.f;
-            hipEvent_t* e = ev_of(s2);
-            HIPCHK(hipEventElapsedTime(&t, e[2 * f], e[2 * f + 1]));
-            kms[f] += t;
-            kcount[f] += 1;
-          }
-      }
-      int any = 0;
-      for (int b = 0; b < nb; ++b) any |= S.h_flags[b];
-      if (!any || it >= o.max_iter + poll) break;
-    }
-    for (auto& e : evs) (void)hipEventDestroy(e);
-    if (gexec) (void)hipGraphExecDestroy(gexec);
-    if (graph) (void)hipGraphDestroy(graph);
-    return it;
-  }
+  // the seed iterations of this solve alone (a batch of one region)
+  int64_t iterate(const scocg_solve_opts& o, double* kms, int64_t* kcount);
 
   // switch the stencil launch shape, growing the partial-sum buffers if needed
   void set_grid(const StencilGrid& g) {
@@ -879,13 +783,18 @@ struct Solver {
     return refined;
   }
 
-  int run(int K, const double* z, int R, const int64_t* rhs_idx, int nS_in, const int64_t* s_idx,
-          const scocg_solve_opts& o, scocg_report* rep) {
+  // ---- phases of a solve (a batch runs the same phases around one shared iteration loop)
+  std::vector<double2> zh;  // energies (host copy)
+  DevBuf zk;                // energies on the device
+  int seed0 = 0;
+
+  // inputs and state; no kernel of the solve proper yet
+  void prepare(int K, const double* z, int R, const int64_t* rhs_idx, int nS_in,
+               const int64_t* s_idx, const scocg_solve_opts& o) {
     const bool full = o.full != 0;
     const int nS = full ? (int)h.N : (s_idx ? nS_in : R);
     hipStream_t st = h.stream;
-    // inputs
-    std::vector<double2> zh(K);
+    zh.resize(K);
     for (int k = 0; k < K; ++k) zh[k] = mk(z[2 * k], z[2 * k + 1]);
     std::vector<int32_t> rh(R);
     for (int j = 0; j < R; ++j) rh[j] = (int32_t)rhs_idx[j];
@@ -895,39 +804,34 @@ struct Solver {
       for (int i = 0; i < nS; ++i) sr[i] = (int32_t)(s_idx ? s_idx[i] : rhs_idx[i]);
       upload(S.srow, sr, st);
     }
-    DevBuf zk;
     upload(zk, zh, st);
     alloc_state(K, R, full, nS, o);
-    const int nb = S.nb;
-    const size_t nkb = (size_t)nb * K * B;
-    const int seed0 = o.init_seed < 0 ? K / 2 : o.init_seed;
+    seed0 = o.init_seed < 0 ? K / 2 : o.init_seed;
+  }
 
-    // autotuning (outside the timed region; cached per shape in the handle)
+  // autotuning (outside the timed region; cached per shape in the handle)
+  double autotune(const scocg_solve_opts& o, int* tuned_now) {
+    *tuned_now = 0;
     const bool auto_tile = o.tile == SCOCG_AUTO, auto_zc = o.zchunk == SCOCG_AUTO,
                auto_kch = o.shift_chunk == SCOCG_AUTO;
-    double tune_ms = 0.0;
-    int tuned_now = 0;
-    if (auto_tile || auto_zc || auto_kch) {
-      const std::array<int64_t, 4> key{B, nb, K, S.nS};
-      auto it = h.tuned.find(key);
-      if (it != h.tuned.end()) {
-        set_grid(plan(nb, auto_tile ? it->second[0] : o.tile, auto_zc ? it->second[1] : o.zchunk));
-        if (auto_kch) S.kch = it->second[2];
-      } else {
-        tune_ms = tune(zk.as<double2>(), seed0, o, auto_tile, auto_zc, auto_kch);
-        tuned_now = 1;
-        h.tuned[key] = {S.g.variant, S.g.zc, S.kch};
-      }
+    if (!(auto_tile || auto_zc || auto_kch)) return 0.0;
+    const std::array<int64_t, 4> key{B, S.nb, S.K, S.nS};
+    auto it = h.tuned.find(key);
+    if (it != h.tuned.end()) {
+      set_grid(plan(S.nb, auto_tile ? it->second[0] : o.tile, auto_zc ? it->second[1] : o.zchunk));
+      if (auto_kch) S.kch = it->second[2];
+      return 0.0;
     }
+    const double ms = tune(zk.as<double2>(), seed0, o, auto_tile, auto_zc, auto_kch);
+    *tuned_now = 1;
+    h.tuned[key] = {S.g.variant, S.g.zc, S.kch};
+    return ms;
+  }
 
-    hipEvent_t e0, e1;
-    HIPCHK(hipEventCreate(&e0));
-    HIPCHK(hipEventCreate(&e1));
-    HIPCHK(hipEventRecord(e0, st));
-    init_unit(zk.as<double2>(), seed0);
-    double kms[SCOCG_K_FAMILIES] = {0};
-    int64_t kcount[SCOCG_K_FAMILIES] = {0};
-    const int64_t it_main = iterate(o, kms, kcount);
+  // after the iterations: trace, FP64 true residuals (full storage) and, for complex64,
+  // refinement; all inside the timed region
+  int64_t post(const scocg_solve_opts& o, int64_t it_main, std::vector<double>& tres) {
+    const size_t nkb = (size_t)S.nb * S.K * B;
     release_workspace();
     if (trace_on()) {
       std::vector<ShiftState> s0(nkb);
@@ -940,29 +844,26 @@ struct Solver {
               (long long)it_main, (long long)n_st[0], (long long)n_st[1], (long long)n_st[2],
               (long long)n_st[4]);
     }
-
-    // FP64 true residuals of every pair (full storage only); refinement passes for
-    // complex64 solves.  Both are inside the timed region.
-    std::vector<double> tres;
     int64_t refined = 0;
     if (S.full && o.refine >= 0) {
       tres = true_residuals(nullptr);
       if (h.precision == SCOCG_MIXED && o.refine > 0) {
         int32_t mx = 0;
-        std::vector<ColState> c0((size_t)nb * B);
+        std::vector<ColState> c0((size_t)S.nb * B);
         HIPCHK(hipMemcpy(c0.data(), S.cols.p, c0.size() * sizeof(ColState), hipMemcpyDeviceToHost));
-        for (int j = 0; j < R; ++j) mx = std::max(mx, c0[j].iters);
+        for (int j = 0; j < S.R; ++j) mx = std::max(mx, c0[j].iters);
         refined = refine(o, o.refine, mx, zh.data(), tres);
       }
     }
-    HIPCHK(hipEventRecord(e1, st));
-    HIPCHK(hipEventSynchronize(e1));
-    float ms = 0.f;
-    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    return refined;
+  }
 
-    // report
+  // fills the report; returns the solve's return code
+  int report(const scocg_solve_opts& o, const std::vector<double>& tres, int64_t refined, float ms,
+             const double* kms, const int64_t* kcount, double tune_ms, int tuned_now,
+             scocg_report* rep) {
+    const int nb = S.nb, K = S.K, R = S.R;
+    const size_t nkb = (size_t)nb * K * B;
     std::vector<ShiftState> shh(nkb);
     std::vector<ColState> ch((size_t)nb * B);
     std::vector<int32_t> bit(nb);
@@ -1017,7 +918,283 @@ struct Solver {
     S.ok = true;
     return rc;
   }
+
+  int run(int K, const double* z, int R, const int64_t* rhs_idx, int nS_in, const int64_t* s_idx,
+          const scocg_solve_opts& o, scocg_report* rep) {
+    hipStream_t st = h.stream;
+    prepare(K, z, R, rhs_idx, nS_in, s_idx, o);
+    int tuned_now = 0;
+    const double tune_ms = autotune(o, &tuned_now);
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    HIPCHK(hipEventRecord(e0, st));
+    init_unit(zk.as<double2>(), seed0);
+    double kms[SCOCG_K_FAMILIES] = {0};
+    int64_t kcount[SCOCG_K_FAMILIES] = {0};
+    const int64_t it_main = iterate(o, kms, kcount);
+    std::vector<double> tres;
+    const int64_t refined = post(o, it_main, tres);
+    HIPCHK(hipEventRecord(e1, st));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return report(o, tres, refined, ms, kms, kcount, tune_ms, tuned_now, rep);
+  }
 };
+
+// Seed iterations of one or more regions (solvers of one precision on one stream,
+// same nf, tile variant and shift chunk): every kernel family is ONE launch per
+// iteration over a device table of per-region arguments; the host polls every
+// region's block flags every `poll` iterations, and the polled iterations can be
+// replayed as one captured hipGraph.
+template <typename T, int B>
+struct Batch {
+  using SV = Solver<T, B>;
+  using cT = typename cplx_of<T>::type;
+  std::vector<SV*> sv;
+  hipStream_t st = nullptr;
+  int nf = 4, variant = 1, kch = 4;
+  bool full = true;
+  DevBuf t_mu, t_upd, t_alpha, t_ctl, t_shift, o_mu, o_upd, o_blk, o_shift;
+  int g_mu = 0, g_upd = 0, g_blk = 0, g_shift = 0;
+  size_t ctl_lds = 0;
+  int timing_mode = 0;
+
+  Batch(std::vector<SV*> v, const scocg_solve_opts& o) : sv(std::move(v)) {
+    require(!sv.empty(), "empty batch");
+    const SV& s0 = *sv[0];
+    st = s0.h.stream;
+    nf = s0.h.nf;
+    variant = s0.S.g.variant;
+    kch = s0.S.kch;
+    std::vector<StencilArgs<T>> mu, up;
+    std::vector<AlphaArgs> al;
+    std::vector<ControlArgs> ct;
+    std::vector<ShiftArgs<T>> sh;
+    std::vector<int32_t> omu{0}, oup{0}, oblk{0}, osh{0};
+    for (SV* p : sv) {
+      auto& S = p->S;
+      auto& h = p->h;
+      require(h.stream == st && h.nf == nf && S.g.variant == variant && S.kch == kch,
+              "batched regions need one stream, one nf, one tile shape and one shift chunk");
+      full = full && p->full_tiles(variant);
+      cT* b0 = S.r0.template as<cT>();
+      cT* b1 = S.r1.template as<cT>();
+      ColState* cols = S.cols.template as<ColState>();
+      int32_t* act = S.blk_active.template as<int32_t>();
+      double2* part0 = S.part0.template as<double2>();
+      double* part1 = S.part1.template as<double>();
+      StencilArgs<T> m = p->stencil_args(MODE_MU, S.g, S.nb, cols, act, part0, nullptr,
+                                         S.dc.template as<cT>(), S.qa.template as<double2>());
+      StencilArgs<T> u = p->stencil_args(MODE_UPDATE, S.g, S.nb, cols, act, part0, part1,
+                                         S.dc.template as<cT>(), nullptr);
+      for (StencilArgs<T>* q : {&m, &u}) {
+        q->pingpong = 1;
+        q->bufs[0] = to_g(b0);
+        q->bufs[1] = to_g(b1);
+      }
+      mu.push_back(m);
+      omu.push_back(omu.back() + SV::stencil_wgs(m, S.g));
+      up.push_back(u);
+      oup.push_back(oup.back() + SV::stencil_wgs(u, S.g));
+      AlphaArgs aa{};
+      aa.part = to_g(part0);
+      aa.nwg = S.nwg;
+      aa.qa = to_g(S.qa.template as<double2>());
+      aa.n_atoms = h.n_atoms;
+      aa.cols = to_g(cols);
+      aa.blk_active = to_g(act);
+      al.push_back(aa);
+      oblk.push_back(oblk.back() + S.nb);
+      ControlArgs ca{};
+      ca.part_rho = to_g(part0);
+      ca.part_nu = to_g(part1);
+      ca.nwg = S.nwg;
+      ca.cols = to_g(cols);
+      ca.sh = to_g(S.sh.template as<ShiftState>());
+      ca.coef = to_g(S.coef.template as<ShiftCoef>());
+      ca.z = to_g(S.z.template as<double2>());
+      ca.K = S.K;
+      ca.list = to_g(S.list.template as<int32_t>());
+      ca.cnt = to_g(S.cnt.template as<int32_t>());
+      ca.k5cnt = to_g(S.k5cnt.template as<int32_t>());
+      ca.blk_active = to_g(act);
+      ca.blk_iter = to_g(S.blk_iter.template as<int32_t>());
+      ca.nb = S.nb;
+      ca.tol = o.tol;
+      ca.max_iter = o.max_iter;
+      ca.seed_switch = o.seed_switch;
+      ca.stall = SV::DBL ? 0 : kStallWindow;
+      ca.floor_est = SV::DBL ? 0.0 : kMixedFloor;
+      ct.push_back(ca);
+      ShiftArgs<T> sa{};
+      sa.rnew[0] = to_g(p->plane0(b0));
+      sa.rnew[1] = to_g(p->plane0(b1));
+      sa.bstride = p->bstride();
+      sa.srow = to_g(S.full ? nullptr : S.srow.template as<int32_t>());
+      sa.nS = S.nS;
+      sa.list = to_g(S.list.template as<int32_t>());
+      sa.k5cnt = to_g(S.k5cnt.template as<int32_t>());
+      sa.K = S.K;
+      sa.nb = S.nb;
+      sa.coef = to_g(S.coef.template as<ShiftCoef>());
+      sa.x = to_g(S.x.template as<double2>());
+      sa.p = to_g(S.p.template as<cT>());
+      sa.gx = (int)nblocks((int64_t)S.nS * B, WG);
+      sa.gy = (int)nblocks(S.K, kch);
+      sh.push_back(sa);
+      const int64_t nsh = (int64_t)osh.back() + (int64_t)sa.gx * sa.gy * S.nb;
+      require(nsh < (int64_t)1 << 31, "shift update grid too large");
+      osh.push_back((int32_t)nsh);
+      ctl_lds = std::max(ctl_lds, SV::control_lds(S.K));
+    }
+    upload(t_mu, mu, st);
+    upload(t_upd, up, st);
+    upload(t_alpha, al, st);
+    upload(t_ctl, ct, st);
+    upload(t_shift, sh, st);
+    upload(o_mu, omu, st);
+    upload(o_upd, oup, st);
+    upload(o_blk, oblk, st);
+    upload(o_shift, osh, st);
+    g_mu = omu.back();
+    g_upd = oup.back();
+    g_blk = oblk.back();
+    g_shift = osh.back();
+    HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_control<B>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)ctl_lds));
+  }
+
+  int n() const { return (int)sv.size(); }
+
+  // ev: null, or 2*SCOCG_K_FAMILIES events recorded around the launches of this
+  // iteration; timing mode 1 records every family, mode 2 only the r_{n+1} pass
+  void mark(hipEvent_t* ev, int fam, int end) {
+    if (!ev || (timing_mode == 2 && fam != SCOCG_K_UPDATE)) return;
+    HIPCHK(hipEventRecord(ev[2 * fam + end], st));
+  }
+
+  template <int KCH>
+  void launch_shift(int par) {
+    hipLaunchKernelGGL((k_shift<T, B, KCH>), dim3(g_shift), dim3(WG), 0, st,
+                       t_shift.as<ShiftArgs<T>>(), o_shift.as<int32_t>(), n(), par);
+    KCHK();
+  }
+
+  void one_iteration(int par, hipEvent_t* ev) {
+    mark(ev, SCOCG_K_MU, 0);
+    SV::template launch_table<MODE_MU>(st, nf, variant, full, t_mu.as<StencilArgs<T>>(),
+                                       o_mu.as<int32_t>(), n(), g_mu, par);
+    mark(ev, SCOCG_K_MU, 1);
+    mark(ev, SCOCG_K_ALPHA, 0);
+    hipLaunchKernelGGL((k_alpha<B>), dim3(g_blk), dim3(WG), 0, st, t_alpha.as<AlphaArgs>(),
+                       o_blk.as<int32_t>(), n(), par);
+    KCHK();
+    mark(ev, SCOCG_K_ALPHA, 1);
+    mark(ev, SCOCG_K_UPDATE, 0);
+    SV::template launch_table<MODE_UPDATE>(st, nf, variant, full, t_upd.as<StencilArgs<T>>(),
+                                           o_upd.as<int32_t>(), n(), g_upd, par);
+    mark(ev, SCOCG_K_UPDATE, 1);
+    mark(ev, SCOCG_K_CONTROL, 0);
+    hipLaunchKernelGGL((k_control<B>), dim3(g_blk), dim3(CT), ctl_lds, st,
+                       t_ctl.as<ControlArgs>(), o_blk.as<int32_t>(), n(), par);
+    KCHK();
+    mark(ev, SCOCG_K_CONTROL, 1);
+    mark(ev, SCOCG_K_SHIFT, 0);
+    switch (kch) {
+      case 1: launch_shift<1>(par); break;
+      case 16: launch_shift<16>(par); break;
+      default: launch_shift<4>(par); break;
+    }
+    mark(ev, SCOCG_K_SHIFT, 1);
+  }
+
+  // Runs until every region's blocks are inactive (or the iteration cap).  With
+  // t0 (an event recorded on the stream before the solve) and region_ms, the device
+  // time from t0 to the poll at which each region finished is stored.
+  int64_t iterate(const scocg_solve_opts& o, double* kms, int64_t* kcount, hipEvent_t t0,
+                  double* region_ms) {
+    int poll = o.poll_every > 0 ? o.poll_every : 16;
+    if (poll & 1) ++poll;  // even: the buffer and list parities return to 0 after each poll
+    int64_t it = 0;
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    // timing: one event pair per kernel family per iteration of a poll chunk
+    timing_mode = o.timing;
+    std::vector<hipEvent_t> evs;
+    if (o.timing) {
+      evs.resize((size_t)poll * 2 * SCOCG_K_FAMILIES);
+      for (auto& e : evs) HIPCHK(hipEventCreate(&e));
+    }
+    hipEvent_t evp = nullptr;
+    if (t0 && region_ms) HIPCHK(hipEventCreate(&evp));
+    std::vector<char> done(sv.size(), 0);
+    auto ev_of = [&](int s2) { return o.timing ? &evs[(size_t)s2 * 2 * SCOCG_K_FAMILIES] : nullptr; };
+    // events recorded during capture cannot be read back after a replay on this
+    // runtime: timing runs use direct launches
+    const bool use_graph = o.use_graph && !o.timing;
+    while (true) {
+      if (use_graph) {
+        if (!gexec) {
+          HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+          for (int s2 = 0; s2 < poll; ++s2) one_iteration(s2 & 1, ev_of(s2));
+          HIPCHK(hipStreamEndCapture(st, &graph));
+          HIPCHK(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+        }
+        HIPCHK(hipGraphLaunch(gexec, st));
+      } else {
+        for (int s2 = 0; s2 < poll; ++s2) one_iteration(s2 & 1, ev_of(s2));
+      }
+      it += poll;
+      if (evp) HIPCHK(hipEventRecord(evp, st));
+      for (SV* p : sv)
+        HIPCHK(hipMemcpyAsync(p->S.h_flags, p->S.blk_active.p, p->S.nb * sizeof(int32_t),
+                              hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      if (o.timing) {
+        for (int s2 = 0; s2 < poll; ++s2)
+          for (int f = 0; f < SCOCG_K_FAMILIES; ++f) {
+            if (f == SCOCG_K_PROJ) continue;  // fused into the MU launch
+            if (o.timing == 2 && f != SCOCG_K_UPDATE) continue;
+            float t = 0.f;
+            hipEvent_t* e = ev_of(s2);
+            HIPCHK(hipEventElapsedTime(&t, e[2 * f], e[2 * f + 1]));
+            kms[f] += t;
+            kcount[f] += 1;
+          }
+      }
+      int any_all = 0;
+      for (size_t r = 0; r < sv.size(); ++r) {
+        int any = 0;
+        for (int b = 0; b < sv[r]->S.nb; ++b) any |= sv[r]->S.h_flags[b];
+        if (!any && !done[r]) {
+          done[r] = 1;
+          if (evp) {
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, t0, evp));
+            region_ms[r] = ms;
+          }
+        }
+        any_all |= any;
+      }
+      if (!any_all || it >= o.max_iter + poll) break;
+    }
+    for (auto& e : evs) (void)hipEventDestroy(e);
+    if (evp) (void)hipEventDestroy(evp);
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    return it;
+  }
+};
+
+template <typename T, int B>
+int64_t Solver<T, B>::iterate(const scocg_solve_opts& o, double* kms, int64_t* kcount) {
+  Batch<T, B> bt({this}, o);
+  return bt.iterate(o, kms, kcount, nullptr, nullptr);
+}
 
 template <typename T, int B>
 void apply_h_impl(scocg_ctx& h, const void* x, void* y) {
@@ -1034,8 +1211,7 @@ void apply_h_impl(scocg_ctx& h, const void* x, void* y) {
   KCHK();
   sv.launch_proj(blk.as<cT>(), 1, dc.as<cT>(), nullptr);
   const auto g = sv.plan(1, 0, 0);
-  sv.template launch_stencil<MODE_APPLY>(blk.as<cT>(), out.as<cT>(), nullptr, nullptr, 1, g,
-                                         nullptr, nullptr, dc.as<cT>());
+  sv.template launch_stencil_once<MODE_APPLY>(blk.as<cT>(), out.as<cT>(), 1, g, dc.as<cT>());
   hipLaunchKernelGGL((k_gather_col0<T, B>), dim3(nblocks(h.N, WG)), dim3(WG), 0, h.stream,
                      out.as<cT>(), static_cast<double2*>(y), h.N, sv.pad_points());
   KCHK();
@@ -1068,6 +1244,108 @@ int guarded(F&& f) {
 }  // namespace
 
 // ------------------------------------------------------------------------------------ C ABI
+namespace {
+
+// argument checks shared by scocg_solve and scocg_batch_solve
+void check_problem(const scocg_ctx* h, int32_t K, const double* z, int32_t R,
+                   const int64_t* rhs_idx, int32_t nS, const int64_t* s_idx, bool full) {
+  require(h != nullptr, "handle is NULL");
+  require(K >= 1 && z != nullptr, "need K >= 1 energies");
+  require(R >= 1 && rhs_idx != nullptr, "need R >= 1 right-hand sides");
+  for (int k = 0; k < K; ++k) {
+    require(std::isfinite(z[2 * k]) && std::isfinite(z[2 * k + 1]), "non-finite energy");
+    require(z[2 * k + 1] > 0.0, "every energy needs Im z > 0");
+  }
+  for (int j = 0; j < R; ++j) require(rhs_idx[j] >= 0 && rhs_idx[j] < h->N, "rhs_idx out of range");
+  if (!full) {
+    if (s_idx) {
+      require(nS >= 1, "nS must be >= 1 with s_idx");
+      for (int i = 0; i < nS; ++i) require(s_idx[i] >= 0 && s_idx[i] < h->N, "s_idx out of range");
+    } else {
+      require(nS == 0, "nS > 0 needs s_idx");
+    }
+  }
+}
+
+scocg_solve_opts check_opts(const scocg_solve_opts* opts) {
+  scocg_solve_opts o{};
+  if (opts) o = *opts;
+  if (!(o.tol > 0.0)) o.tol = 1e-10;
+  require(std::isfinite(o.tol), "non-finite tol");
+  if (o.max_iter <= 0) o.max_iter = 100000;
+  require(o.timing >= 0 && o.timing <= 2, "timing must be 0, 1 or 2");
+  require(o.tile >= SCOCG_AUTO && o.tile <= 4, "tile must be SCOCG_AUTO or 0..4");
+  require(o.zchunk >= SCOCG_AUTO, "zchunk must be SCOCG_AUTO or >= 0");
+  require(o.shift_chunk == SCOCG_AUTO || o.shift_chunk == 0 || o.shift_chunk == 1 ||
+              o.shift_chunk == 4 || o.shift_chunk == 16,
+          "shift_chunk must be SCOCG_AUTO, 0, 1, 4 or 16");
+  return o;
+}
+
+// All regions: prepare, one shared iteration loop (one launch per kernel family per
+// iteration), then per region the FP64 checks / refinement and the report.
+template <typename T, int B>
+int run_batch(int n, const scocg_handle* hs, const scocg_problem* pr, scocg_solve_opts o,
+              scocg_report* reps, double* region_ms) {
+  // one launch shape for all regions: autotuning is not offered here
+  if (o.tile == SCOCG_AUTO) o.tile = 0;
+  if (o.zchunk == SCOCG_AUTO) o.zchunk = 0;
+  if (o.shift_chunk == SCOCG_AUTO) o.shift_chunk = 0;
+  std::vector<std::unique_ptr<Solver<T, B>>> sv;
+  std::vector<Solver<T, B>*> ptr;
+  for (int i = 0; i < n; ++i) {
+    hs[i]->last.reset(new scocg_ctx::Solve());
+    sv.emplace_back(new Solver<T, B>(*hs[i], *hs[i]->last));
+    scocg_solve_opts oi = o;
+    if (oi.init_seed >= pr[i].K) oi.init_seed = -1;
+    sv.back()->prepare(pr[i].K, pr[i].z, pr[i].R, pr[i].rhs_idx, pr[i].nS, pr[i].s_idx, oi);
+    ptr.push_back(sv.back().get());
+  }
+  hipStream_t st = hs[0]->stream;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  HIPCHK(hipEventRecord(e0, st));
+  for (auto* p : ptr) p->init_unit(p->zk.template as<double2>(), p->seed0);
+  double kms[SCOCG_K_FAMILIES] = {0};
+  int64_t kcount[SCOCG_K_FAMILIES] = {0};
+  std::vector<double> done_ms(n, 0.0);
+  int64_t it_main = 0;
+  {
+    Batch<T, B> bt(ptr, o);
+    it_main = bt.iterate(o, kms, kcount, e0, done_ms.data());
+  }
+  std::vector<std::vector<double>> tres(n);
+  std::vector<int64_t> refined(n, 0);
+  for (int i = 0; i < n; ++i) {
+    refined[i] = ptr[i]->post(o, it_main, tres[i]);
+    // refinement, where it runs, extends the region's completion past the loop
+    if (!tres[i].empty() && refined[i] > 0) {
+      HIPCHK(hipEventRecord(e1, st));
+      HIPCHK(hipEventSynchronize(e1));
+      float t = 0.f;
+      HIPCHK(hipEventElapsedTime(&t, e0, e1));
+      done_ms[i] = t;
+    }
+  }
+  HIPCHK(hipEventRecord(e1, st));
+  HIPCHK(hipEventSynchronize(e1));
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  int rc = SCOCG_OK;
+  for (int i = 0; i < n; ++i) {
+    const int r = ptr[i]->report(o, tres[i], refined[i], ms, kms, kcount, 0.0, 0,
+                                 reps ? &reps[i] : nullptr);
+    if (r == SCOCG_BREAKDOWN || (r == SCOCG_NOT_ALL_CONVERGED && rc == SCOCG_OK)) rc = r;
+    if (region_ms) region_ms[i] = done_ms[i];
+  }
+  return rc;
+}
+
+}  // namespace
+
 extern "C" {
 
 int scocg_create(const scocg_grid* g, const double* coef, const double* vloc, int32_t n_atoms,
@@ -1133,38 +1411,14 @@ int scocg_create(const scocg_grid* g, const double* coef, const double* vloc, in
   });
 }
 
+
 int scocg_solve(scocg_handle h, int32_t K, const double* z, int32_t R, const int64_t* rhs_idx,
                 int32_t nS, const int64_t* s_idx, const scocg_solve_opts* opts,
                 scocg_report* rep) {
   return guarded([&]() -> int {
-    require(h != nullptr, "handle is NULL");
-    require(K >= 1 && z != nullptr, "need K >= 1 energies");
-    require(R >= 1 && rhs_idx != nullptr, "need R >= 1 right-hand sides");
-    for (int k = 0; k < K; ++k) {
-      require(std::isfinite(z[2 * k]) && std::isfinite(z[2 * k + 1]), "non-finite energy");
-      require(z[2 * k + 1] > 0.0, "every energy needs Im z > 0");
-    }
-    for (int j = 0; j < R; ++j) require(rhs_idx[j] >= 0 && rhs_idx[j] < h->N, "rhs_idx out of range");
-    scocg_solve_opts o{};
-    if (opts) o = *opts;
-    if (!(o.tol > 0.0)) o.tol = 1e-10;
-    require(std::isfinite(o.tol), "non-finite tol");
-    if (o.max_iter <= 0) o.max_iter = 100000;
+    const scocg_solve_opts o = check_opts(opts);
+    check_problem(h, K, z, R, rhs_idx, nS, s_idx, o.full != 0);
     require(o.init_seed >= -1 && o.init_seed < K, "init_seed out of range");
-    require(o.timing >= 0 && o.timing <= 2, "timing must be 0, 1 or 2");
-    require(o.tile >= SCOCG_AUTO && o.tile <= 4, "tile must be SCOCG_AUTO or 0..4");
-    require(o.zchunk >= SCOCG_AUTO, "zchunk must be SCOCG_AUTO or >= 0");
-    require(o.shift_chunk == SCOCG_AUTO || o.shift_chunk == 0 || o.shift_chunk == 1 ||
-                o.shift_chunk == 4 || o.shift_chunk == 16,
-            "shift_chunk must be SCOCG_AUTO, 0, 1, 4 or 16");
-    if (!o.full) {
-      if (s_idx) {
-        require(nS >= 1, "nS must be >= 1 with s_idx");
-        for (int i = 0; i < nS; ++i) require(s_idx[i] >= 0 && s_idx[i] < h->N, "s_idx out of range");
-      } else {
-        require(nS == 0, "nS > 0 needs s_idx");
-      }
-    }
     HIPCHK(hipSetDevice(h->device));
     h->last.reset(new scocg_ctx::Solve());
     if (h->precision == SCOCG_FP64) {
@@ -1173,6 +1427,27 @@ int scocg_solve(scocg_handle h, int32_t K, const double* z, int32_t R, const int
     }
     Solver<float, 16> sv(*h, *h->last);
     return sv.run(K, z, R, rhs_idx, nS, s_idx, o, rep);
+  });
+}
+
+int scocg_batch_solve(int32_t n, const scocg_handle* hs, const scocg_problem* probs,
+                      const scocg_solve_opts* opts, scocg_report* reps, double* region_ms) {
+  return guarded([&]() -> int {
+    require(n >= 1 && hs != nullptr && probs != nullptr, "need n >= 1 handles and problems");
+    const scocg_solve_opts o = check_opts(opts);
+    require(o.init_seed == -1, "init_seed must be -1 (each region's middle energy) in a batch");
+    for (int i = 0; i < n; ++i) {
+      const scocg_problem& p = probs[i];
+      check_problem(hs[i], p.K, p.z, p.R, p.rhs_idx, p.nS, p.s_idx, o.full != 0);
+      require(hs[i]->device == hs[0]->device && hs[i]->stream == hs[0]->stream,
+              "batched handles need one device and one stream");
+      require(hs[i]->precision == hs[0]->precision && hs[i]->nf == hs[0]->nf,
+              "batched handles need one precision and one nf");
+      for (int j = 0; j < i; ++j) require(hs[j] != hs[i], "a handle appears twice in the batch");
+    }
+    HIPCHK(hipSetDevice(hs[0]->device));
+    if (hs[0]->precision == SCOCG_FP64) return run_batch<double, 8>(n, hs, probs, o, reps, region_ms);
+    return run_batch<float, 16>(n, hs, probs, o, reps, region_ms);
   });
 }
 
@@ -1243,6 +1518,7 @@ int64_t scocg_struct_size(int32_t which) {
     case 0: return (int64_t)sizeof(scocg_grid);
     case 1: return (int64_t)sizeof(scocg_solve_opts);
     case 2: return (int64_t)sizeof(scocg_report);
+    case 3: return (int64_t)sizeof(scocg_problem);
     default: return 0;
   }
 }

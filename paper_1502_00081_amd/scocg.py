@@ -22,8 +22,8 @@ FP64, MIXED = 0, 1
 PAIR_CONVERGED, PAIR_MAXITER, PAIR_BREAKDOWN, PAIR_STALLED = 0, 1, 2, 4
 C128, C64 = 0, 1
 
-EXPORTS = ("scocg_create", "scocg_solve", "scocg_green_columns", "scocg_apply_h",
-           "scocg_destroy", "scocg_last_error", "scocg_struct_size")
+EXPORTS = ("scocg_create", "scocg_solve", "scocg_batch_solve", "scocg_green_columns",
+           "scocg_apply_h", "scocg_destroy", "scocg_last_error", "scocg_struct_size")
 AUTO = -1  # SCOCG_AUTO: autotuned launch shape
 
 
@@ -47,6 +47,11 @@ class Report(C.Structure):
                 ("kernel_ms", C.c_double * 6), ("kernel_launches", C.c_int64 * 6),
                 ("tile_used", C.c_int32), ("zchunk_used", C.c_int32),
                 ("shift_chunk_used", C.c_int32), ("tuned", C.c_int32), ("tune_ms", C.c_double)]
+
+class Problem(C.Structure):
+    _fields_ = [("K", C.c_int32), ("z", C.c_void_p), ("R", C.c_int32), ("rhs_idx", C.c_void_p),
+                ("nS", C.c_int32), ("s_idx", C.c_void_p)]
+
 
 KERNEL_FAMILIES = ("proj", "mu", "alpha", "update", "control", "shift")
 
@@ -86,7 +91,9 @@ def load(path: str = LIB_PATH):
     lib.scocg_last_error.restype = C.c_char_p
     lib.scocg_struct_size.argtypes = [C.c_int32]
     lib.scocg_struct_size.restype = C.c_int64
-    for which, mirror in enumerate((Grid, SolveOpts, Report)):
+    lib.scocg_batch_solve.argtypes = [C.c_int32, P, P, C.POINTER(SolveOpts), P, P]
+    lib.scocg_batch_solve.restype = C.c_int
+    for which, mirror in enumerate((Grid, SolveOpts, Report, Problem)):
         if lib.scocg_struct_size(which) != C.sizeof(mirror):
             raise RuntimeError(f"{path}: {mirror.__name__} is {C.sizeof(mirror)} bytes here, "
                                f"{lib.scocg_struct_size(which)} in the library")
@@ -118,6 +125,32 @@ def _dev_ptr(t):
     return int(t.data_ptr()) if hasattr(t, "data_ptr") else int(t)
 
 
+def _opts(tol, max_iter, init_seed, seed_switch, full, refine, poll_every, use_graph, timing,
+          tile, zchunk, shift_chunk):
+    return SolveOpts(float(tol), int(max_iter), int(init_seed), int(bool(seed_switch)),
+                     int(bool(full)), int(refine), int(poll_every), int(bool(use_graph)),
+                     int(timing), int(tile), int(zchunk), int(shift_chunk))
+
+
+def _new_report(K, R):
+    arrays = dict(iters=np.zeros((K, R), np.int64), est=np.zeros((K, R)),
+                  true_resid=np.zeros((K, R)), status=np.zeros((K, R), np.int32))
+    rep = Report()
+    rep.iters, rep.est_resid = arrays["iters"].ctypes.data, arrays["est"].ctypes.data
+    rep.true_resid, rep.status = arrays["true_resid"].ctypes.data, arrays["status"].ctypes.data
+    return rep, arrays
+
+
+def _report_dict(rep, arrays):
+    return dict(arrays, seed_iters=rep.seed_iters, n_switches=rep.n_switches,
+                refined=rep.refined, solve_ms=rep.solve_ms, block_iters=rep.block_iters,
+                block_width=rep.block_width, n_blocks=rep.n_blocks,
+                kernel_ms=dict(zip(KERNEL_FAMILIES, list(rep.kernel_ms))),
+                kernel_launches=dict(zip(KERNEL_FAMILIES, list(rep.kernel_launches))),
+                tile=rep.tile_used, zchunk=rep.zchunk_used, shift_chunk=rep.shift_chunk_used,
+                tuned=bool(rep.tuned), tune_ms=rep.tune_ms)
+
+
 class Handle:
     """One uploaded Hamiltonian (scocg_create) and its last solve."""
 
@@ -134,36 +167,17 @@ class Handle:
         lib = load()
         z = _c(z, np.complex128)
         rhs = _c(rhs_idx, np.int64)
-        K, R = z.size, rhs.size
-        sp = None
-        nS = 0
-        if s_idx is not None:
-            sp = _c(s_idx, np.int64)
-            nS = sp.size
-        o = SolveOpts(float(tol), int(max_iter), int(init_seed), int(bool(seed_switch)),
-                      int(bool(full)), int(refine), int(poll_every), int(bool(use_graph)),
-                      int(timing), int(tile), int(zchunk), int(shift_chunk))
-        iters = np.zeros((K, R), np.int64)
-        est = np.zeros((K, R))
-        tres = np.zeros((K, R))
-        status = np.zeros((K, R), np.int32)
-        rep = Report()
-        rep.iters, rep.est_resid = iters.ctypes.data, est.ctypes.data
-        rep.true_resid, rep.status = tres.ctypes.data, status.ctypes.data
-        rc = lib.scocg_solve(self._h, K, z.ctypes.data, R, rhs.ctypes.data, nS,
+        sp = None if s_idx is None else _c(s_idx, np.int64)
+        o = _opts(tol, max_iter, init_seed, seed_switch, full, refine, poll_every, use_graph,
+                  timing, tile, zchunk, shift_chunk)
+        rep, arrays = _new_report(z.size, rhs.size)
+        rc = lib.scocg_solve(self._h, z.size, z.ctypes.data, rhs.size, rhs.ctypes.data,
+                             0 if sp is None else sp.size,
                              None if sp is None else sp.ctypes.data, C.byref(o), C.byref(rep))
         _check(rc)
-        nrows = self.n if full else (nS if sp is not None else R)
-        self.last = (K, R, nrows)
-        return rc, dict(iters=iters, est=est, true_resid=tres, status=status,
-                        seed_iters=rep.seed_iters, n_switches=rep.n_switches,
-                        refined=rep.refined, solve_ms=rep.solve_ms, block_iters=rep.block_iters,
-                        block_width=rep.block_width, n_blocks=rep.n_blocks,
-                        kernel_ms=dict(zip(KERNEL_FAMILIES, list(rep.kernel_ms))),
-                        kernel_launches=dict(zip(KERNEL_FAMILIES, list(rep.kernel_launches))),
-                        tile=rep.tile_used, zchunk=rep.zchunk_used,
-                        shift_chunk=rep.shift_chunk_used, tuned=bool(rep.tuned),
-                        tune_ms=rep.tune_ms)
+        nrows = self.n if full else (sp.size if sp is not None else rhs.size)
+        self.last = (z.size, rhs.size, nrows)
+        return rc, _report_dict(rep, arrays)
 
     def green_columns(self, out=None, dtype=C128):
         """scocg_green_columns into `out` (torch device tensor or numpy array), or a new
@@ -222,3 +236,33 @@ def create_from_problem(p, precision=FP64, stream=None) -> Handle:
     """scocg_create for an object with the fields of workload.Problem."""
     return create(p.nx, p.ny, p.nz, p.nf, p.coef, p.vloc, p.atom_ptr, p.atom_idx, p.atom_P,
                   p.atom_D, precision=precision, stream=stream)
+
+
+def batch_solve(handles, problems, tol=1e-10, max_iter=100000, seed_switch=True, full=False,
+                refine=0, poll_every=0, use_graph=False, timing=0, tile=0, zchunk=0,
+                shift_chunk=0):
+    """scocg_batch_solve over regions; problems: [(z, rhs_idx) or (z, rhs_idx, s_idx)].
+    Returns (rc, [report dict per region], region_ms [n])."""
+    lib = load()
+    n = len(handles)
+    assert len(problems) == n
+    keep, probs, reps, arrays = [], (Problem * n)(), (Report * n)(), []
+    for i, pr in enumerate(problems):
+        z = _c(pr[0], np.complex128)
+        rhs = _c(pr[1], np.int64)
+        sp = _c(pr[2], np.int64) if len(pr) > 2 and pr[2] is not None else None
+        keep += [z, rhs, sp]
+        probs[i] = Problem(z.size, z.ctypes.data, rhs.size, rhs.ctypes.data,
+                           0 if sp is None else sp.size, None if sp is None else sp.ctypes.data)
+        rep, arr = _new_report(z.size, rhs.size)
+        reps[i] = rep
+        arrays.append(arr)
+        nrows = handles[i].n if full else (sp.size if sp is not None else rhs.size)
+        handles[i].last = (z.size, rhs.size, nrows)
+    hs = (C.c_void_p * n)(*[h._h.value for h in handles])
+    o = _opts(tol, max_iter, -1, seed_switch, full, refine, poll_every, use_graph, timing, tile,
+              zchunk, shift_chunk)
+    region_ms = np.zeros(n)
+    rc = lib.scocg_batch_solve(n, hs, probs, C.byref(o), reps, region_ms.ctypes.data)
+    _check(rc)
+    return rc, [_report_dict(reps[i], arrays[i]) for i in range(n)], region_ms

@@ -467,3 +467,51 @@ def test_peapod_shape_sampled_pairs_full_storage(dev):
         assert np.abs(g - g.T).max() <= 2 * tol / eta
         assert (np.diag(g).imag < 0).all()
         assert np.abs(g).max() <= 1.0 / eta
+
+
+@pytest.mark.parametrize("prec", [scocg.FP64, scocg.MIXED])
+def test_batch_of_uneven_regions_matches_single_solves(dev, prec):
+    """Three regions of different depth, energy count and column count (one with
+    projectors) in one batched solve -- one launch per kernel family per iteration --
+    give bit for bit the single solves' Green's functions, iteration counts and
+    statuses (complex64 with full storage and refinement included); every region
+    reports a completion time within the batch."""
+    regs = [small(16, 16, 10, 4, False, K=5, nb=2, nt=2, seed=3),
+            small(16, 16, 20, 4, True, K=9, nb=5, nt=4, seed=4),
+            W.tiny_fp64()]
+    full = prec == scocg.MIXED
+    kw = dict(tol=1e-10 if prec == scocg.FP64 else 1e-8, full=full, refine=3 if full else 0)
+    stream = torch.cuda.Stream()
+    hs = [scocg.create_from_problem(p, precision=prec, stream=stream) for p in regs]
+    single = []
+    for h, p in zip(hs, regs):
+        rc, rep = h.solve(p.z, p.rhs_idx, **kw)
+        single.append((rc, rep, h.green_columns()))
+    rc, reps, region_ms = scocg.batch_solve(hs, [(p.z, p.rhs_idx) for p in regs],
+                                            use_graph=True, **kw)
+    say(f"batch prec={prec}: rc={rc}, region ms {np.round(region_ms, 2)}, "
+        f"iterations {[r['seed_iters'] for r in reps]}")
+    for i, (h, p) in enumerate(zip(hs, regs)):
+        rc1, rep1, G1 = single[i]
+        assert np.array_equal(h.green_columns(), G1), i
+        assert np.array_equal(reps[i]["iters"], rep1["iters"]), i
+        assert np.array_equal(reps[i]["status"], rep1["status"]), i
+        assert reps[i]["seed_iters"] == rep1["seed_iters"]
+        assert 0 < region_ms[i] <= reps[i]["solve_ms"] * 1.0001
+    assert rc == max(s[0] for s in single)
+    for h in hs:
+        h.destroy()
+
+
+def test_batch_rejects_mismatched_handles(dev):
+    p = small(16, 16, 10, 4, False, K=4, nb=2, nt=2, seed=3)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    a = scocg.create_from_problem(p, precision=scocg.FP64, stream=s1)
+    b = scocg.create_from_problem(p, precision=scocg.FP64, stream=s2)
+    c = scocg.create_from_problem(p, precision=scocg.MIXED, stream=s1)
+    for hs in ([a, b], [a, c], [a, a]):
+        with pytest.raises(scocg.ScocgError) as e:
+            scocg.batch_solve(hs, [(p.z, p.rhs_idx)] * len(hs))
+        assert e.value.code == scocg.EINVAL
+    for h in (a, b, c):
+        h.destroy()

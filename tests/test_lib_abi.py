@@ -81,11 +81,12 @@ def test_solve_and_copy_reject_null_handle():
 
 
 def test_struct_sizes_match_binding():
-    """The ctypes mirrors of scocg_grid, scocg_solve_opts and scocg_report have the
+    """The ctypes mirrors of scocg_grid, scocg_solve_opts, scocg_report and scocg_problem have the
     library's sizes (load() refuses a mismatch); unknown ids give 0."""
     import ctypes as C
     lib = scocg.load()
     assert lib.scocg_struct_size(0) == C.sizeof(scocg.Grid)
     assert lib.scocg_struct_size(1) == C.sizeof(scocg.SolveOpts)
     assert lib.scocg_struct_size(2) == C.sizeof(scocg.Report)
+    assert lib.scocg_struct_size(3) == C.sizeof(scocg.Problem)
     assert lib.scocg_struct_size(7) == 0
