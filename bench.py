@@ -53,6 +53,8 @@ def parse():
                     help="skip the untimed per-family timing solve")
     ap.add_argument("--fixed-shape", action="store_true",
                     help="default launch shape instead of the autotuned one")
+    ap.add_argument("--no-sequential", action="store_true",
+                    help="batched_regions: skip the region-by-region comparison")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed-vs-FP64 comparison on the 16x16x24 all-plane workload")
     return ap.parse_args()
@@ -158,6 +160,54 @@ def mixed_vs_fp64(tol):
     return res
 
 
+def batched_regions_run(a):
+    """The 12 uneven regions (32x32x48 .. 32x32x224) solved to tol in one batched solve
+    (one launch per kernel family per iteration), then each region alone: converged
+    pairs per second both ways and the per-region completion times of the batch."""
+    import torch
+    from paper_1502_00081_amd import scocg, workload
+    regs = workload.batched_regions()
+    prec = scocg.FP64 if a.precision == "fp64" else scocg.MIXED
+    stream = torch.cuda.Stream()
+    hs = [scocg.create_from_problem(p, precision=prec, stream=stream) for p in regs]
+    kw = dict(tol=a.tol, use_graph=True, max_iter=a.max_iter if a.max_iter > 0 else 400000)
+    pairs = sum(p.z.size * p.rhs_idx.size for p in regs)
+    say(f"batched regions: {len(regs)} regions, {pairs} pairs, precision {a.precision}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc, reps, region_ms = scocg.batch_solve(hs, [(p.z, p.rhs_idx) for p in regs], **kw)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    conv = sum(int((r["status"] == scocg.PAIR_CONVERGED).sum()) for r in reps)
+    say(f"batched: rc={rc}, {conv}/{pairs} converged in {tb:.1f} s")
+    ts, conv_s = 0.0, 0
+    if not a.no_sequential:
+        for i, (h, p) in enumerate(zip(hs, regs)):
+            t1 = time.perf_counter()
+            rc1, rep1 = h.solve(p.z, p.rhs_idx, **kw)
+            torch.cuda.synchronize()
+            ts += time.perf_counter() - t1
+            conv_s += int((rep1["status"] == scocg.PAIR_CONVERGED).sum())
+            say(f"region {i} alone: {rep1['seed_iters']} iterations, {time.perf_counter() - t1:.1f} s")
+    for h in hs:
+        h.destroy()
+    line = {"metric": "converged (shift x column) solves/s at 1e-8 rel residual, batched regions",
+            "value": conv / tb, "unit": "solves/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+            "ms_per_step": tb * 1e3, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f64" if prec == scocg.FP64 else "c64-vectors/f64-scalars",
+            "data": "synthetic",
+            "config": {"workload": "batched_regions_12x32x32xnz", "regions": len(regs),
+                       "pairs": pairs, "tol": a.tol, "precision": a.precision},
+            "converged": conv,
+            "region_completion_ms": {"p50": float(np.percentile(region_ms, 50)),
+                                     "p99": float(np.percentile(region_ms, 99)),
+                                     "all": [round(float(x), 1) for x in region_ms]},
+            "region_seed_iters": [int(r["seed_iters"]) for r in reps]}
+    if not a.no_sequential:
+        line["sequential"] = {"solves_per_s": conv_s / ts, "seconds": ts, "converged": conv_s}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -168,6 +218,9 @@ def main():
     from paper_1502_00081_amd import scocg, workload
 
     assert torch.cuda.is_available(), "bench.py needs a ROCm GPU"
+    if a.workload == "batched_regions":
+        batched_regions_run(a)
+        return
     p = workload.WORKLOADS[a.workload]()
     prec = scocg.FP64 if a.precision == "fp64" else scocg.MIXED
     stream = torch.cuda.current_stream()

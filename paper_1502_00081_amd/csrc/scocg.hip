@@ -85,13 +85,16 @@ void upload(DevBuf& b, const std::vector<U>& v, hipStream_t s) {
 unsigned nblocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 // SCOCG_TRACE=1 prints per-pass refinement statistics to stderr
-bool trace_on() {
-  static const bool on = [] {
+// SCOCG_TRACE=1: solve summaries on stderr; 2: also a progress line every 2048 seed
+// iterations (long solves)
+int trace_level() {
+  static const int lv = [] {
     const char* e = getenv("SCOCG_TRACE");
-    return e && *e && *e != '0';
+    return e ? atoi(e) : 0;
   }();
-  return on;
+  return lv;
 }
+bool trace_on() { return trace_level() > 0; }
 
 }  // namespace
 
@@ -1179,6 +1182,12 @@ struct Batch {
           }
         }
         any_all |= any;
+      }
+      if (trace_level() >= 2 && it % 2048 == 0) {
+        int left = 0;
+        for (char d : done) left += !d;
+        fprintf(stderr, "[scocg] %lld seed iterations, %d of %d regions active\n", (long long)it,
+                left, (int)sv.size());
       }
       if (!any_all || it >= o.max_iter + poll) break;
     }

@@ -515,3 +515,47 @@ def test_batch_rejects_mismatched_handles(dev):
         assert e.value.code == scocg.EINVAL
     for h in (a, b, c):
         h.destroy()
+
+
+@pytest.mark.timeout(600)
+def test_batched_uneven_regions_full_size_capped(dev):
+    """The 12 uneven regions (32x32x48 .. 32x32x224, 64..384 energies, 32..256 columns)
+    at full size in one batch, capped at 1024 seed iterations: two regions re-solved
+    alone with the same cap give the same bits; pairs still running report status
+    max-iter; the fastest-converging pairs of three regions match the oracle."""
+    regs = W.batched_regions()
+    cap = 1024
+    stream = torch.cuda.Stream()
+    hs = [scocg.create_from_problem(p, precision=scocg.FP64, stream=stream) for p in regs]
+    t0 = time.time()
+    rc, reps, region_ms = scocg.batch_solve(hs, [(p.z, p.rhs_idx) for p in regs], tol=1e-8,
+                                            max_iter=cap, use_graph=True)
+    say(f"batch of 12 regions capped at {cap}: rc={rc}, {time.time() - t0:.1f} s, "
+        f"{sum(int((r['status'] == 0).sum()) for r in reps)} pairs converged")
+    assert rc == scocg.NOT_ALL_CONVERGED
+    G = [h.green_columns() for h in hs]
+    for r in reps:
+        st = r["status"]
+        assert ((st == scocg.PAIR_CONVERGED) | (st == scocg.PAIR_MAXITER)).all()
+        assert (r["iters"][st == scocg.PAIR_MAXITER] >= cap).all()
+        assert (r["iters"][st == scocg.PAIR_CONVERGED] <= r["seed_iters"]).all()
+    for i in (0, 7):
+        rc1, rep1 = hs[i].solve(regs[i].z, regs[i].rhs_idx, tol=1e-8, max_iter=cap)
+        assert np.array_equal(hs[i].green_columns(), G[i]), i
+        assert np.array_equal(rep1["iters"], reps[i]["iters"]), i
+        assert np.array_equal(rep1["status"], reps[i]["status"]), i
+    for h in hs:
+        h.destroy()
+    for i in (0, 5, 11):
+        p, r = regs[i], reps[i]
+        conv = np.argwhere(r["status"] == scocg.PAIR_CONVERGED)
+        if conv.size == 0:
+            continue
+        k, j = conv[np.argmin(r["iters"][conv[:, 0], conv[:, 1]])]
+        ref, it, st, _ = oracle.cocg_unit_columns(p, p.z, p.rhs_idx, p.rhs_idx,
+                                                  [(int(k), int(j))], tol=1e-10)
+        eta = p.z.imag.min()
+        d = np.linalg.norm(G[i][k, j] - ref[0])
+        say(f"region {i} pair ({k},{j}): {r['iters'][k, j]} GPU / {int(it[0])} oracle "
+            f"iterations, |dG| {d:.2e}")
+        assert d <= (1e-8 + 1e-10) / eta
