@@ -191,6 +191,29 @@ __device__ __forceinline__ V ld_or_zero(const V* p, bool ok) {
   return csel(ok, *p, z);
 }
 
+// Streaming accesses that are not re-read by another workgroup (r_{n-1} in, r_{n+1}
+// out): nontemporal, so they do not displace the r_n planes whose halos neighbouring
+// workgroups still read from L2.
+template <typename V>
+__device__ __forceinline__ V ld_stream(const V* p) {
+  using E = decltype(p->x);
+  typedef E v2 __attribute__((ext_vector_type(2)));
+  const v2 t = __builtin_nontemporal_load(reinterpret_cast<const v2*>(p));
+  V r;
+  r.x = t.x;
+  r.y = t.y;
+  return r;
+}
+template <typename V>
+__device__ __forceinline__ void st_stream(V* p, V v) {
+  using E = decltype(v.x);
+  typedef E v2 __attribute__((ext_vector_type(2)));
+  v2 t;
+  t.x = v.x;
+  t.y = v.y;
+  __builtin_nontemporal_store(t, reinterpret_cast<v2*>(p));
+}
+
 __device__ __forceinline__ int wrapi(int v, int n) {
   v %= n;
   return v < 0 ? v + n : v;
@@ -335,6 +358,7 @@ struct StencilWG {
   cT* iodst;       // UPDATE/APPLY output (padded, block 0)
   char* smem;
   int c, cb, z0, z1, nxy;
+  int zmir;  // >= 0: this z-chunk marches downwards (physical plane = zmir - virtual)
   const char* rbase;  // uniform: this block's vector, first padding plane
   char* iobase;       // uniform: the UPDATE/APPLY output vector of this block
   uint32_t pstride;   // bytes per plane
@@ -416,13 +440,26 @@ struct StencilWG {
     zi = (T)zs.y;
     acc0 = mk(0, 0);
     acc1 = 0.0;
-    // queue planes z0-NF .. z0+NF-1 (padded indices z0 .. z0+2NF-1) into slots
-    // 0 .. 2NF-1 (rotation 0); ragged points keep zeros
+    // odd z-chunks of the UPDATE/APPLY passes march downwards: the queue planes that
+    // neighbouring chunks share are then read by both at about the same time (both
+    // chunks start, or both end, at their common boundary), and the second read hits
+    // L2.  The march runs over virtual planes z0..z1-1 either way; a downward chunk
+    // maps virtual plane v to z0+z1-1-v (the operator is symmetric in z).  The
+    // symmetric mu form counts forward pairs and keeps every chunk upwards.
+    zmir = (!SYM && (zci & 1)) ? z0 + z1 - 1 : -1;
+    // queue planes z0-NF .. z0+NF-1 into slots 0 .. 2NF-1 (rotation 0); ragged points
+    // keep zeros.  The symmetric form reads only the forward z-neighbours, so its
+    // planes below z0 stay zero, unread.
 #pragma unroll
     for (int m = 0; m < OPT; ++m) {
 #pragma unroll
       for (int d = 0; d < 2 * NF; ++d) {
-        cT v = ldr((uint32_t)(z0 + d), qoff[m]);
+        if (SYM && d < NF) {
+          Q[m][d].x = 0;
+          Q[m][d].y = 0;
+          continue;
+        }
+        cT v = ldr((uint32_t)(pz(z0 - NF + d) + NF), qoff[m]);
         if (!FULL) {
           cT zero;
           zero.x = 0;
@@ -436,30 +473,35 @@ struct StencilWG {
     return true;
   }
 
-  // queue entry of plane iz+NF for owned points (a ragged point instead takes
-  // the wrapped value of plane iz, which only fills its LDS slot); r_{n-1} at
+  // physical plane of virtual plane v (uniform)
+  __device__ __forceinline__ int pz(int v) const { return zmir >= 0 ? zmir - v : v; }
+
+  // queue entry of virtual plane iz+NF for owned points (a ragged point instead
+  // takes the wrapped value of plane iz, which only fills its LDS slot); r_{n-1} at
   // plane iz; halo ring of plane iz
   __device__ __forceinline__ void prefetch(int iz) {
+    const uint32_t pc = (uint32_t)(pz(iz) + NF);  // padded physical index of plane iz
 #pragma unroll
     for (int m = 0; m < OPT; ++m) {
-      const int zq = (FULL || val[m]) ? iz + 2 * NF : iz + NF;  // padded plane index
-      pq[m] = ldr((uint32_t)zq, qoff[m]);
+      const uint32_t zq = (FULL || val[m]) ? (uint32_t)(pz(iz + NF) + NF) : pc;
+      pq[m] = ldr(zq, qoff[m]);
       if (MODE == MODE_UPDATE)
-        pp[m] = *reinterpret_cast<const cT*>(iobase + (uint32_t)(iz + NF) * pstride + qoff[m]);
+        pp[m] = ld_stream(reinterpret_cast<const cT*>(iobase + pc * pstride + qoff[m]));
     }
 #pragma unroll
-    for (int i = 0; i < HPT; ++i) ph[i] = ldr((uint32_t)(iz + NF), hoff[i]);
+    for (int i = 0; i < HPT; ++i) ph[i] = ldr(pc, hoff[i]);
   }
 
-  // one plane with queue rotation S: logical queue index d (plane iz-NF+d) lives
-  // in slot (d + S) % W
+  // one (virtual) plane with queue rotation S: logical queue index d (plane
+  // iz-NF+d) lives in slot (d + S) % W
   template <int S>
   __device__ __forceinline__ void step(int iz) {
     constexpr int snew = (2 * NF + S) % W;
     constexpr int sctr = (NF + S) % W;
     cT* lds = reinterpret_cast<cT*>(smem + ((iz - z0) & 1) * TILE_BYTES);
     // V and the projector range of this plane (the barrier covers part of their latency)
-    const T* vb = a.vloc + (int64_t)iz * nxy;
+    const int ip = pz(iz);  // physical plane
+    const T* vb = a.vloc + (int64_t)ip * nxy;
     T cv[OPT];
     int ce0[OPT], ce1[OPT];
     cT cp[OPT];
@@ -469,7 +511,7 @@ struct StencilWG {
       if (MODE != MODE_MU) {
         ce0[m] = ce1[m] = 0;
         if (a.prow) {  // uniform branch
-          const int32_t* pr = a.prow + (int64_t)iz * nxy + gq[m];
+          const int32_t* pr = a.prow + (int64_t)ip * nxy + gq[m];
           ce0[m] = pr[0];
           ce1[m] = pr[1];
         }
@@ -553,7 +595,7 @@ struct StencilWG {
             hi = fmat(pvv[l], d.y, hi);
           }
         }
-        cT* op = reinterpret_cast<cT*>(iobase + (uint32_t)(iz + NF) * pstride + qoff[m]);
+        cT* op = reinterpret_cast<cT*>(iobase + (uint32_t)(ip + NF) * pstride + qoff[m]);
         if (MODE == MODE_APPLY) {
           cT o;
           o.x = hr;
@@ -579,7 +621,7 @@ struct StencilWG {
           rn.y = __builtin_fma(ap.x, rp.y, rn.y);
           rn.y = __builtin_fma(ap.y, rp.x, rn.y);
           const cT rs = from_d<cT>(rn);
-          *op = rs;
+          st_stream(op, rs);
           const double2 rq = to_d(rs);
           acc0.x = __builtin_fma(rq.x, rq.x, __builtin_fma(-rq.y, rq.y, acc0.x));
           acc0.y = __builtin_fma(2.0 * rq.x, rq.y, acc0.y);
