@@ -61,7 +61,7 @@ def parse():
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stencil_update_medium_fp64.txt")
-KERNEL_SOURCES = ("paper_1502_00081_amd/csrc/kernels.hpp", "paper_1502_00081_amd/csrc/scocg.hip")
+KERNEL_SOURCES = ("paper_1502_00081_amd/csrc/kernels.hpp",)  # the device code
 
 
 def kernel_source_hash():
@@ -73,10 +73,11 @@ def kernel_source_hash():
     return d.hexdigest()[:16]
 
 
-def measured_traffic(workload, precision):
+def measured_traffic(workload, precision, tile, zchunk):
     """HBM bytes per launch of the r_{n+1} pass from the committed counter summary
     (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's readings); None when the
-    summary is missing, covers another workload, or the kernels changed since."""
+    summary is missing, covers another workload or launch shape, or the device code
+    changed since."""
     try:
         with open(TRAFFIC_FILE) as fh:
             kv = dict(l.split(":", 1) for l in fh if ":" in l and not l.startswith("#"))
@@ -84,6 +85,7 @@ def measured_traffic(workload, precision):
         return None, None
     kv = {k.strip(): v.strip() for k, v in kv.items()}
     if (kv.get("workload") != workload or kv.get("precision") != precision
+            or kv.get("tile") != str(tile) or kv.get("zchunk") != str(zchunk)
             or kv.get("kernel_source_sha256_16") != kernel_source_hash()):
         return None, None
     return float(kv["traffic_bytes_per_launch"]), float(kv["algorithmic_bytes_per_launch"])
@@ -269,7 +271,8 @@ def main():
     upd_ms = sum(r["kernel_ms"]["update"] for r in reps)
     upd_launches = sum(r["kernel_launches"]["update"] for r in reps)
     achieved = upd_bytes / (upd_ms * 1e-3) / 1e9
-    traffic, traffic_alg = measured_traffic(p.name, a.precision)
+    traffic, traffic_alg = measured_traffic(p.name, a.precision, reps[-1]["tile"],
+                                            reps[-1]["zchunk"])
     line = {
         "metric": "converged (shift x column) solves/s at 1e-8 rel residual",
         "value": converged / dt,
