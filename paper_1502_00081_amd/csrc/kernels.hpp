@@ -333,8 +333,12 @@ __device__ __forceinline__ float fmat<float>(float a, float b, float c) {
 template <typename T, int NF, int B, int MODE, int TX, int TY, int NT, bool FULL>
 struct StencilWG {
   using cT = typename cplx_of<T>::type;
-  static constexpr int W = 2 * NF + 1;
+  // z-queue: logical index d holds plane iz - LO + d, d = 0 .. W-1.  The UPDATE and
+  // APPLY passes need planes iz-NF .. iz+NF; the symmetric mu form only the centre
+  // and its forward neighbours iz .. iz+NF, which halves its queue registers.
   static constexpr bool SYM = MODE == MODE_MU;
+  static constexpr int LO = SYM ? 0 : NF;
+  static constexpr int W = SYM ? NF + 1 : 2 * NF + 1;
   static constexpr int O = SYM ? 0 : NF;  // interior origin inside the LDS tile
   static constexpr int PX = TX + (SYM ? NF : 2 * NF);
   static constexpr int PY = TY + (SYM ? NF : 2 * NF);
@@ -447,19 +451,13 @@ struct StencilWG {
     // maps virtual plane v to z0+z1-1-v (the operator is symmetric in z).  The
     // symmetric mu form counts forward pairs and keeps every chunk upwards.
     zmir = (!SYM && (zci & 1)) ? z0 + z1 - 1 : -1;
-    // queue planes z0-NF .. z0+NF-1 into slots 0 .. 2NF-1 (rotation 0); ragged points
-    // keep zeros.  The symmetric form reads only the forward z-neighbours, so its
-    // planes below z0 stay zero, unread.
+    // queue planes z0-LO .. z0-LO+W-2 into slots 0 .. W-2 (rotation 0); the first
+    // step fills slot W-1; ragged points keep zeros
 #pragma unroll
     for (int m = 0; m < OPT; ++m) {
 #pragma unroll
-      for (int d = 0; d < 2 * NF; ++d) {
-        if (SYM && d < NF) {
-          Q[m][d].x = 0;
-          Q[m][d].y = 0;
-          continue;
-        }
-        cT v = ldr((uint32_t)(pz(z0 - NF + d) + NF), qoff[m]);
+      for (int d = 0; d < W - 1; ++d) {
+        cT v = ldr((uint32_t)(pz(z0 - LO + d) + NF), qoff[m]);
         if (!FULL) {
           cT zero;
           zero.x = 0;
@@ -493,11 +491,11 @@ struct StencilWG {
   }
 
   // one (virtual) plane with queue rotation S: logical queue index d (plane
-  // iz-NF+d) lives in slot (d + S) % W
+  // iz-LO+d) lives in slot (d + S) % W
   template <int S>
   __device__ __forceinline__ void step(int iz) {
-    constexpr int snew = (2 * NF + S) % W;
-    constexpr int sctr = (NF + S) % W;
+    constexpr int snew = (W - 1 + S) % W;  // plane iz + NF, prefetched
+    constexpr int sctr = (LO + S) % W;     // plane iz
     cT* lds = reinterpret_cast<cT*>(smem + ((iz - z0) & 1) * TILE_BYTES);
     // V and the projector range of this plane (the barrier covers part of their latency)
     const int ip = pz(iz);  // physical plane
@@ -545,13 +543,22 @@ struct StencilWG {
         T fr = 0, fi = 0;
 #pragma unroll
         for (int k = 1; k <= NF; ++k) {
-          const cT zp = Q[m][(NF + k + S) % W];
-          const cT xp = L[k * B];
-          const cT yp = L[k * PX * B];
+          const cT zp = Q[m][(LO + k + S) % W];
           fr = fmat(a.co.cz[k], zp.x, fr);
           fi = fmat(a.co.cz[k], zp.y, fi);
+        }
+        // x then y neighbours from LDS, fenced so that at most NF reads are in flight
+        // (the 64-VGPR budget of two workgroups per CU)
+#pragma unroll
+        for (int k = 1; k <= NF; ++k) {
+          const cT xp = L[k * B];
           fr = fmat(a.co.cx[k], xp.x, fr);
           fi = fmat(a.co.cx[k], xp.y, fi);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int k = 1; k <= NF; ++k) {
+          const cT yp = L[k * PX * B];
           fr = fmat(a.co.cy[k], yp.x, fr);
           fi = fmat(a.co.cy[k], yp.y, fi);
         }
@@ -566,7 +573,7 @@ struct StencilWG {
         T hr = dg * ctr.x, hi = dg * ctr.y;
 #pragma unroll
         for (int k = 1; k <= NF; ++k) {
-          const cT zp = Q[m][(NF + k + S) % W], zm = Q[m][(NF - k + S) % W];
+          const cT zp = Q[m][(LO + k + S) % W], zm = Q[m][(LO - k + S) % W];
           hr = fmat(a.co.cz[k], zp.x + zm.x, hr);
           hi = fmat(a.co.cz[k], zp.y + zm.y, hi);
         }
@@ -676,8 +683,11 @@ struct StencilWG {
 // contraction of r_n: the first nproj_wg workgroups (a multiple of 8, so the
 // XCD slicing of the stencil workgroups is unchanged) each contract one
 // (atom, column block).
+// The mu pass fits two 1024-thread workgroups per CU (8 waves per SIMD, its short
+// queue and one-sided halo keep it within 64 VGPRs and 62 KB of LDS); the others one.
 template <typename T, int NF, int B, int MODE, int TX, int TY, int NT, bool FULL>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ __launch_bounds__(NT)
+__attribute__((amdgpu_waves_per_eu(MODE == MODE_MU && NT == 1024 ? 8 : 4)))
 void k_stencil(const StencilArgs<T>* __restrict__ regs, const int32_t* __restrict__ off,
                int nreg, int cur) {
   using SW = StencilWG<T, NF, B, MODE, TX, TY, NT, FULL>;
