@@ -53,6 +53,8 @@ def parse():
                     help="skip the untimed per-family timing solve")
     ap.add_argument("--fixed-shape", action="store_true",
                     help="default launch shape instead of the autotuned one")
+    ap.add_argument("--shape", default="",
+                    help="explicit launch shape 'tile,zchunk,shift_chunk' (no autotuning)")
     ap.add_argument("--no-sequential", action="store_true",
                     help="batched_regions: skip the region-by-region comparison")
     ap.add_argument("--no-mixed", action="store_true",
@@ -230,7 +232,11 @@ def main():
     K, R = p.z.size, p.rhs_idx.size
     out = torch.empty((K, R, R), dtype=torch.complex128, device="cuda")
     kw = dict(tol=a.tol, timing=2)
-    if not a.fixed_shape:  # autotuned in the first (warmup) solve, cached in the handle
+    if a.shape:
+        t_, z_, k_ = (int(x) for x in a.shape.split(","))
+        kw.update(tile=t_, zchunk=z_, shift_chunk=k_)
+        a.fixed_shape = True
+    elif not a.fixed_shape:  # autotuned in the first (warmup) solve, cached in the handle
         kw.update(tile=scocg.AUTO, zchunk=scocg.AUTO, shift_chunk=scocg.AUTO)
     if a.max_iter > 0:
         kw["max_iter"] = a.max_iter

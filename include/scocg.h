@@ -125,7 +125,7 @@ typedef struct {
 
 /* Autotuning: any of tile, zchunk, shift_chunk = SCOCG_AUTO makes scocg_solve time
    short trial runs (16 seed iterations from the initial state of this very problem)
-   of each candidate launch shape -- the 4 tile shapes x up to 4 z-chunk lengths around
+   of each candidate launch shape -- the 4 tile shapes x up to 6 z-chunk lengths around
    the default, then 3 shift chunks -- before the solve proper, keep the fastest, and
    cache it in the handle for this (column blocks, energies, rows) shape; later solves
    of that shape reuse it.  Trials run outside the timed region (scocg_report.tune_ms

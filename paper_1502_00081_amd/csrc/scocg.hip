@@ -627,7 +627,7 @@ struct Solver {
         const StencilGrid g0 = plan(S.nb, v, want_zc ? 0 : o.zchunk);
         std::vector<int> zcs = {g0.zc};
         if (want_zc)
-          for (int zc : {g0.zc / 2, g0.zc * 2, g0.zc * 4})
+          for (int zc : {g0.zc / 2, g0.zc * 4 / 3, g0.zc * 3 / 2, g0.zc * 2, g0.zc * 4})
             if (zc >= 4 && zc <= h.nz) zcs.push_back(zc);
         std::sort(zcs.begin(), zcs.end());
         zcs.erase(std::unique(zcs.begin(), zcs.end()), zcs.end());
