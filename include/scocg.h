@@ -138,7 +138,8 @@ typedef struct {
 #define SCOCG_K_ALPHA 2    /* seed alpha_n, c_n */
 #define SCOCG_K_UPDATE 3   /* stencil pass: r_{n+1} (three-term recurrence) + dot partials */
 #define SCOCG_K_CONTROL 4  /* beta_n, pi recurrences, convergence, compaction, seed switch */
-#define SCOCG_K_SHIFT 5    /* x^(k), p^(k) on the rows S */
+#define SCOCG_K_SHIFT 5    /* (reported as 0: the x^(k), p^(k) update of iteration n runs in the
+                              SCOCG_K_MU launch of iteration n + 1) */
 #define SCOCG_K_FAMILIES 6
 
 typedef struct {

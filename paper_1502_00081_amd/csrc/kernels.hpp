@@ -2,7 +2,8 @@
 //
 // Data layout in HBM (B = columns per block, 8 for complex128, 16 for complex64,
 // so one grid point of one block is 128 contiguous bytes):
-//   Krylov vectors      [nb][N][B]        complex<T>   (RHS innermost)
+//   Krylov vectors      [nb][nz+2nf][nx*ny][B] complex<T> (RHS innermost; nf zero planes
+//                       below and above the grid)
 //   shift vectors x, p  [nb][K][nS][B]    x complex128, p complex<T>
 //   shift state         [nb][K][B]        ShiftState (pi_{n-1}, pi_n, status)
 //   column state        [nb*B]            ColState (seed scalars, FP64)
@@ -14,7 +15,8 @@
 //                     over r_{n-1}; partials of rho_{n+1}, ||r_{n+1}||^2
 //   k_control   beta_n (Eq. A6); pi, alpha^(i), beta^(i) per shift (Eqs. A8-A10);
 //               convergence, compaction of active shifts; seed switch (Eq. A13)
-//   k_shift     x^(i), p^(i) on the rows S (Eqs. A11-A12 with Eq. A7)
+//   x^(i), p^(i) on the rows S (Eqs. A11-A12 with Eq. A7): in extra workgroups of the
+//               next iteration's k_stencil<MU> launch (k_shift after the last iteration)
 // A r_n is recomputed in the UPDATE pass instead of being stored, so one
 // iteration streams r_n twice, r_{n-1} once and writes r_{n+1} once.
 #pragma once
@@ -142,6 +144,23 @@ struct ProjArgs {
 };
 
 template <typename T>
+struct ShiftArgs {
+  using cT = typename cplx_of<T>::type;
+  gptr<const cT> rnew[2];          // plane 0 of the Krylov buffers; r_{n+1} is rnew[par ^ 1]
+  int64_t bstride;            // elements per column block
+  gptr<const int32_t> srow;        // [nS] rows S (null: all N rows)
+  int nS;
+  gptr<const int32_t> list;        // [2][nb][K] active shift lists (read list[par])
+  gptr<const int32_t> k5cnt;       // [nb] entries of the list this iteration
+  int K, nb;
+  gptr<const ShiftCoef> coef;      // [nb][K][B]
+  gptr<double2> x;                 // [nb][K][nS][B]
+  gptr<cT> p;                      // [nb][K][nS][B]
+  int gx, gy;                 // workgroups per block along rows and along the list
+  int kch;                    // list entries (energies) per workgroup
+};
+
+template <typename T>
 struct StencilArgs {
   using cT = typename cplx_of<T>::type;
   gptr<const cT> r;           // [nb][nz+2NF][nxy][B] stored r_n, from the first padding plane
@@ -167,6 +186,8 @@ struct StencilArgs {
   gptr<double> part1;         // [nb][nwg][B] ||r||^2 partials (UPDATE)
   int nproj_wg;          // MU: leading workgroups doing the projector contraction
   ProjArgs<T> proj;
+  int nshift_wg;         // MU: next workgroups doing the previous iteration's x, p update
+  ShiftArgs<T> shift;
 };
 
 // Component-wise select of two complex values taken by value.  Register arrays
@@ -715,6 +736,15 @@ void k_stencil(const StencilArgs<T>* __restrict__ regs, const int32_t* __restric
     }
     bid -= a.nproj_wg;
   }
+  if (MODE == MODE_MU && a.nshift_wg > 0) {
+    // the previous iteration's x, p update (parity cur ^ 1): it reads r_n[S], which
+    // this pass only reads, and x, p, which no other workgroup touches
+    if (bid < a.nshift_wg) {
+      if (bid < a.shift.gx * a.shift.gy * a.shift.nb) shift_body<T, B, NT>(a.shift, bid, cur ^ 1);
+      return;
+    }
+    bid -= a.nshift_wg;
+  }
   // XCD-aware decode of the logical stencil workgroup id
   const int ntile = a.ntx * a.nty;
   const int total = a.nb * a.nzc * ntile;
@@ -1099,39 +1129,20 @@ __global__ __launch_bounds__(CT) void k_control(const ControlArgs* __restrict__ 
 //   x^(k) += alpha^(k)_n p^(k);   p^(k) = r_{n+1}[S] / pi_{n+1} + beta^(k)_n p^(k)
 // grid: (ceil(nS*B/WG), ceil(K/KCH), nb); each thread owns one (row of S, column)
 // and walks a chunk of the block's active shift list.
-template <typename T>
-struct ShiftArgs {
-  using cT = typename cplx_of<T>::type;
-  gptr<const cT> rnew[2];          // plane 0 of the Krylov buffers; r_{n+1} is rnew[par ^ 1]
-  int64_t bstride;            // elements per column block
-  gptr<const int32_t> srow;        // [nS] rows S (null: all N rows)
-  int nS;
-  gptr<const int32_t> list;        // [2][nb][K] active shift lists (read list[par])
-  gptr<const int32_t> k5cnt;       // [nb] entries of the list this iteration
-  int K, nb;
-  gptr<const ShiftCoef> coef;      // [nb][K][B]
-  gptr<double2> x;                 // [nb][K][nS][B]
-  gptr<cT> p;                      // [nb][K][nS][B]
-  int gx, gy;                 // workgroups per block along rows and along the list
-};
 
-// x^(k) += alpha^(k) p^(k);  p^(k) = r_{n+1}[S] / pi^(k)_{n+1} + beta^(k) p^(k)  (Eqs. A11-A12):
-// per region gx * gy * nb workgroups: WG rows of S x KCH list entries x column block.
-template <typename T, int B, int KCH>
-__global__ __launch_bounds__(WG) void k_shift(const ShiftArgs<T>* __restrict__ regs,
-                                               const int32_t* __restrict__ off, int nreg,
-                                               int par) {
+// x^(k) += alpha^(k) p^(k);  p^(k) = r_{n+1}[S] / pi^(k)_{n+1} + beta^(k) p^(k)  (Eqs. A11-A12)
+// for workgroup lb of one region (NTH threads): gx * gy * nb workgroups, NTH rows of S
+// x kch list entries x column block.  par: parity of the iteration being completed.
+template <typename T, int B, int NTH>
+__device__ __forceinline__ void shift_body(const ShiftArgs<T>& a, int lb, int par) {
   using cT = typename cplx_of<T>::type;
-  const int rg = region_of(off, nreg, blockIdx.x);
-  const ShiftArgs<T> a = regs[rg];
-  const int lb = blockIdx.x - off[rg];
   const int bx = lb % a.gx, by = (lb / a.gx) % a.gy, cb = lb / (a.gx * a.gy);
   const int cnt = a.k5cnt[cb];
-  const int e0 = by * KCH;
+  const int e0 = by * a.kch;
   if (e0 >= cnt) return;
-  const int e1 = min(e0 + KCH, cnt);
+  const int e1 = min(e0 + a.kch, cnt);
   const int nS = a.nS, K = a.K;
-  const int64_t gid = (int64_t)bx * WG + threadIdx.x;
+  const int64_t gid = (int64_t)bx * NTH + threadIdx.x;
   if (gid >= (int64_t)nS * B) return;
   const int i = (int)(gid / B), c = (int)(gid % B);
   const int64_t row = a.srow ? (int64_t)a.srow[i] : (int64_t)i;
@@ -1151,6 +1162,17 @@ __global__ __launch_bounds__(WG) void k_shift(const ShiftArgs<T>* __restrict__ r
     x[vo] = cadd(xv, cmul(cf.a, pv));
     p[vo] = from_d<cT>(cadd(cmul(cf.f, rv), cmul(cf.b, pv)));
   }
+}
+
+// Stand-alone x, p update of the last iteration of a solve (every other iteration's
+// update runs in the next mu launch, overlapped with its stencil workgroups).
+template <typename T, int B>
+__global__ __launch_bounds__(WG) void k_shift(const ShiftArgs<T>* __restrict__ regs,
+                                               const int32_t* __restrict__ off, int nreg,
+                                               int par) {
+  const int rg = region_of(off, nreg, blockIdx.x);
+  const ShiftArgs<T> a = regs[rg];
+  shift_body<T, B, WG>(a, blockIdx.x - off[rg], par);
 }
 
 // ------------------------------------------------------------------ initialisation

@@ -300,6 +300,27 @@ struct Solver {
     return h.nf == 4 && h.nx % tc.tx == 0 && h.ny % tc.ty == 0;
   }
 
+  // x^(k), p^(k) update arguments for workgroups of nth threads, kch energies each
+  ShiftArgs<T> shift_args(int nth, int kch) const {
+    ShiftArgs<T> sa{};
+    sa.rnew[0] = to_g(plane0(S.r0.template as<cT>()));
+    sa.rnew[1] = to_g(plane0(S.r1.template as<cT>()));
+    sa.bstride = bstride();
+    sa.srow = S.full ? nullptr : to_g(S.srow.template as<int32_t>());
+    sa.nS = S.nS;
+    sa.list = to_g(S.list.template as<int32_t>());
+    sa.k5cnt = to_g(S.k5cnt.template as<int32_t>());
+    sa.K = S.K;
+    sa.nb = S.nb;
+    sa.coef = to_g(S.coef.template as<ShiftCoef>());
+    sa.x = to_g(S.x.template as<double2>());
+    sa.p = to_g(S.p.template as<cT>());
+    sa.gx = (int)nblocks((int64_t)S.nS * B, nth);
+    sa.gy = (int)nblocks(S.K, kch);
+    sa.kch = kch;
+    return sa;
+  }
+
   // One region's arguments of a stencil pass.  MODE_MU with qa != null also contracts
   // the projectors (into dc and qa) in nproj_wg leading workgroups.  r/io (or the
   // ping-pong pair) are filled by the caller.
@@ -332,7 +353,9 @@ struct Solver {
   }
 
   // workgroups of one region in a stencil launch
-  static int stencil_wgs(const StencilArgs<T>& a, const StencilGrid& g) { return g.grid + a.nproj_wg; }
+  static int stencil_wgs(const StencilArgs<T>& a, const StencilGrid& g) {
+    return g.grid + a.nproj_wg + a.nshift_wg;
+  }
 
   template <int MODE, int NF, int TX, int TY, int NT>
   static void launch_v(hipStream_t st, bool full, const StencilArgs<T>* regs, const int32_t* off,
@@ -992,6 +1015,9 @@ struct Batch {
       double* part1 = S.part1.template as<double>();
       StencilArgs<T> m = p->stencil_args(MODE_MU, S.g, S.nb, cols, act, part0, nullptr,
                                          S.dc.template as<cT>(), S.qa.template as<double2>());
+      // x, p update of iteration n inside the mu launch of iteration n + 1
+      m.shift = p->shift_args(SV::tile_cfg(h.nf == 4 ? variant : 1).nt, kch);
+      m.nshift_wg = (m.shift.gx * m.shift.gy * S.nb + 7) / 8 * 8;
       StencilArgs<T> u = p->stencil_args(MODE_UPDATE, S.g, S.nb, cols, act, part0, part1,
                                          S.dc.template as<cT>(), nullptr);
       for (StencilArgs<T>* q : {&m, &u}) {
@@ -1033,21 +1059,7 @@ struct Batch {
       ca.stall = SV::DBL ? 0 : kStallWindow;
       ca.floor_est = SV::DBL ? 0.0 : kMixedFloor;
       ct.push_back(ca);
-      ShiftArgs<T> sa{};
-      sa.rnew[0] = to_g(p->plane0(b0));
-      sa.rnew[1] = to_g(p->plane0(b1));
-      sa.bstride = p->bstride();
-      sa.srow = to_g(S.full ? nullptr : S.srow.template as<int32_t>());
-      sa.nS = S.nS;
-      sa.list = to_g(S.list.template as<int32_t>());
-      sa.k5cnt = to_g(S.k5cnt.template as<int32_t>());
-      sa.K = S.K;
-      sa.nb = S.nb;
-      sa.coef = to_g(S.coef.template as<ShiftCoef>());
-      sa.x = to_g(S.x.template as<double2>());
-      sa.p = to_g(S.p.template as<cT>());
-      sa.gx = (int)nblocks((int64_t)S.nS * B, WG);
-      sa.gy = (int)nblocks(S.K, kch);
+      const ShiftArgs<T> sa = p->shift_args(WG, kch);
       sh.push_back(sa);
       const int64_t nsh = (int64_t)osh.back() + (int64_t)sa.gx * sa.gy * S.nb;
       require(nsh < (int64_t)1 << 31, "shift update grid too large");
@@ -1080,13 +1092,6 @@ struct Batch {
     HIPCHK(hipEventRecord(ev[2 * fam + end], st));
   }
 
-  template <int KCH>
-  void launch_shift(int par) {
-    hipLaunchKernelGGL((k_shift<T, B, KCH>), dim3(g_shift), dim3(WG), 0, st,
-                       t_shift.as<ShiftArgs<T>>(), o_shift.as<int32_t>(), n(), par);
-    KCHK();
-  }
-
   void one_iteration(int par, hipEvent_t* ev) {
     mark(ev, SCOCG_K_MU, 0);
     SV::template launch_table<MODE_MU>(st, nf, variant, full, t_mu.as<StencilArgs<T>>(),
@@ -1106,13 +1111,14 @@ struct Batch {
                        t_ctl.as<ControlArgs>(), o_blk.as<int32_t>(), n(), par);
     KCHK();
     mark(ev, SCOCG_K_CONTROL, 1);
-    mark(ev, SCOCG_K_SHIFT, 0);
-    switch (kch) {
-      case 1: launch_shift<1>(par); break;
-      case 16: launch_shift<16>(par); break;
-      default: launch_shift<4>(par); break;
-    }
-    mark(ev, SCOCG_K_SHIFT, 1);
+    // the x, p update of this iteration runs in the next mu launch (or the flush)
+  }
+
+  // x, p update of the last iteration run (parity par)
+  void flush_shift(int par) {
+    hipLaunchKernelGGL((k_shift<T, B>), dim3(g_shift), dim3(WG), 0, st,
+                       t_shift.as<ShiftArgs<T>>(), o_shift.as<int32_t>(), n(), par);
+    KCHK();
   }
 
   // Runs until every region's blocks are inactive (or the iteration cap).  With
@@ -1160,7 +1166,8 @@ struct Batch {
       if (o.timing) {
         for (int s2 = 0; s2 < poll; ++s2)
           for (int f = 0; f < SCOCG_K_FAMILIES; ++f) {
-            if (f == SCOCG_K_PROJ) continue;  // fused into the MU launch
+            // the projector contraction and the x, p update run inside the MU launch
+            if (f == SCOCG_K_PROJ || f == SCOCG_K_SHIFT) continue;
             if (o.timing == 2 && f != SCOCG_K_UPDATE) continue;
             float t = 0.f;
             hipEvent_t* e = ev_of(s2);
@@ -1191,6 +1198,8 @@ struct Batch {
       }
       if (!any_all || it >= o.max_iter + poll) break;
     }
+    // every poll chunk ends with an odd-parity iteration (poll is even)
+    flush_shift(1);
     for (auto& e : evs) (void)hipEventDestroy(e);
     if (evp) (void)hipEventDestroy(evp);
     if (gexec) (void)hipGraphExecDestroy(gexec);

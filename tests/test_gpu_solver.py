@@ -198,7 +198,8 @@ def test_repeatable_and_graph_replay_bitwise(dev):
         if tm == 0:
             assert sum(n.values()) == 0
         elif tm == 1:
-            assert n["proj"] == 0 and all(n[f] > 0 for f in ("mu", "alpha", "update", "control", "shift"))
+            assert n["proj"] == 0 and n["shift"] == 0  # both run inside the mu launch
+            assert all(n[f] > 0 for f in ("mu", "alpha", "update", "control"))
             assert n["update"] == n["mu"] and rep["kernel_ms"]["update"] > 0
         else:
             assert n["update"] > 0 and sum(n.values()) == n["update"]
