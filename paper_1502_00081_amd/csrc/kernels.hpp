@@ -857,7 +857,7 @@ struct ControlArgs {
 // per-column reduction is one fixed-order tree over the CT/B lanes of that
 // column.  Activity flags and |pi_{n+1}| of the block live in dynamic LDS
 // ([K][B] each) between the phases; the compaction uses wave ballots.
-constexpr int CT = 512;  // threads of the control kernel
+constexpr int CT = 1024;  // threads of the control kernel
 
 template <int B>
 __global__ __launch_bounds__(CT) void k_control(const ControlArgs* __restrict__ regs,
