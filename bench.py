@@ -212,6 +212,39 @@ def batched_regions_run(a):
     print(json.dumps(line), flush=True)
 
 
+def sweep_run(a):
+    """Conventional vs shifted COCG as the number of energies grows (the comparison the
+    paper makes in Sec. 3C): the 16x16x24 workload (all 8 columns) and the medium
+    workload restricted to 8 columns, energies evenly spread over each window."""
+    import torch
+    from paper_1502_00081_amd import scocg, workload
+    out = []
+    for name, p, Ks, tol in (("tiny_fp64", workload.tiny_fp64(), (1, 2, 4, 8, 16), 1e-10),
+                             ("medium_fp64 (8 columns)", workload.medium_fp64(), (1, 2, 4, 8, 16),
+                              1e-8)):
+        rhs = p.rhs_idx[:8]
+        h = scocg.create_from_problem(p, precision=scocg.FP64, stream=torch.cuda.current_stream())
+        for K in Ks:
+            ks = np.linspace(0, p.z.size - 1, K).round().astype(int) if K > 1 else [p.z.size // 2]
+            z = p.z[ks]
+            row = {"workload": name, "energies": K, "columns": int(rhs.size)}
+            for mode, conv in (("shifted", False), ("conventional", True)):
+                h.solve(z, rhs, tol=tol, use_graph=True, conventional=conv)  # warm
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                rc, rep = h.solve(z, rhs, tol=tol, use_graph=True, conventional=conv)
+                torch.cuda.synchronize()
+                row[mode] = {"ms": (time.perf_counter() - t0) * 1e3,
+                             "seed_iters": int(rep["seed_iters"]),
+                             "converged": int((rep["status"] == scocg.PAIR_CONVERGED).sum())}
+            say(f"sweep {name} K={K}: shifted {row['shifted']['ms']:.1f} ms, conventional "
+                f"{row['conventional']['ms']:.1f} ms")
+            out.append(row)
+        h.destroy()
+    print(json.dumps({"metric": "solve time vs number of energies, shifted vs conventional COCG",
+                      "unit": "ms", "data": "synthetic", "sweep": out}), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -224,6 +257,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a ROCm GPU"
     if a.workload == "batched_regions":
         batched_regions_run(a)
+        return
+    if a.workload == "sweep":
+        sweep_run(a)
         return
     p = workload.WORKLOADS[a.workload]()
     prec = scocg.FP64 if a.precision == "fp64" else scocg.MIXED

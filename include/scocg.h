@@ -121,6 +121,10 @@ typedef struct {
                             SCOCG_AUTO: autotuned) */
     int32_t shift_chunk; /* energies per workgroup of the x^(k), p^(k) update: 1, 4 or 16
                             (0 -> 4; SCOCG_AUTO: autotuned) */
+    int32_t conventional; /* 1: the conventional COCG sweep the shifted method is compared
+                            with (Sec. 3C): every (energy, column) pair runs its own
+                            recurrence, nothing is shared between energies; outputs and
+                            report as for the shifted solve */
 } scocg_solve_opts;
 
 /* Autotuning: any of tile, zchunk, shift_chunk = SCOCG_AUTO makes scocg_solve time

@@ -543,7 +543,8 @@ struct Solver {
   }
 
   // unit right-hand sides e_{rhs[j]}, energies zk[K] shared by every column
-  void init_unit(const double2* zk, int seed0) {
+  // zpc (K == 1 only): one energy per column instead of zk[K] shared by all columns
+  void init_unit(const double2* zk, int seed0, const double2* zpc = nullptr) {
     hipStream_t st = h.stream;
     const int nb = S.nb, K = S.K, R = S.R;
     const size_t nkb = (size_t)nb * K * B;
@@ -557,7 +558,7 @@ struct Solver {
     KCHK();
     hipLaunchKernelGGL((k_init_state<B>), dim3(nblocks((int64_t)nkb, WG)), dim3(WG), 0, st,
                        S.cols.as<ColState>(), S.sh.as<ShiftState>(), S.coef.as<ShiftCoef>(),
-                       S.z.as<double2>(), zk, nullptr, nullptr, K, nb, R, seed0, S.list.as<int32_t>(),
+                       S.z.as<double2>(), zk, zpc, nullptr, K, nb, R, seed0, S.list.as<int32_t>(),
                        S.cnt.as<int32_t>(), S.k5cnt.as<int32_t>(), S.blk_active.as<int32_t>(),
                        S.blk_iter.as<int32_t>());
     KCHK();
@@ -613,7 +614,7 @@ struct Solver {
     ot.timing = 0;
     ot.use_graph = 0;
     ot.poll_every = iters;
-    init_unit(zk, seed0);
+    init_unit(zk, seed0, conv ? zk : nullptr);
     hipEvent_t a, b;
     HIPCHK(hipEventCreate(&a));
     HIPCHK(hipEventCreate(&b));
@@ -724,7 +725,7 @@ struct Solver {
           back.push_back(t);
           // the corrected residual is ||t|| times the inner relative residual
           tolc.push_back(std::min(0.5, std::max(1e-12, 0.25 * o.tol / t)));
-          zp.push_back(zk_host[k]);
+          zp.push_back(conv ? zcol[(size_t)cb * B + c] : zk_host[k]);
           tmax = std::max(tmax, t);
         }
     if (kb.empty()) return 0;
@@ -811,8 +812,10 @@ struct Solver {
 
   // ---- phases of a solve (a batch runs the same phases around one shared iteration loop)
   std::vector<double2> zh;  // energies (host copy)
-  DevBuf zk;                // energies on the device
+  DevBuf zk;                // energies on the device (conventional: one per column)
   int seed0 = 0;
+  bool conv = false;              // conventional sweep: column k*R + j solves (z_k - H) x = e_j
+  std::vector<double2> zcol;      // conventional: energy of every column (padded to whole blocks)
 
   // inputs and state; no kernel of the solve proper yet
   void prepare(int K, const double* z, int R, const int64_t* rhs_idx, int nS_in,
@@ -830,9 +833,28 @@ struct Solver {
       for (int i = 0; i < nS; ++i) sr[i] = (int32_t)(s_idx ? s_idx[i] : rhs_idx[i]);
       upload(S.srow, sr, st);
     }
-    upload(zk, zh, st);
-    alloc_state(K, R, full, nS, o);
-    seed0 = o.init_seed < 0 ? K / 2 : o.init_seed;
+    conv = o.conventional != 0;
+    if (!conv) {
+      upload(zk, zh, st);
+      alloc_state(K, R, full, nS, o);
+      seed0 = o.init_seed < 0 ? K / 2 : o.init_seed;
+      return;
+    }
+    // conventional sweep: K*R single-energy systems, column k*R + j = (z_k, e_{rhs_j}); the
+    // report and output layouts [1][K*R] and [1][K*R][nS] are those of [K][R] and [K][R][nS]
+    const int64_t RC = (int64_t)K * R;
+    require(RC <= INT32_MAX / B, "too many (energy, column) pairs for the conventional sweep");
+    std::vector<int32_t> rc((size_t)RC);
+    zcol.assign((size_t)((RC + B - 1) / B) * B, zh[K - 1]);
+    for (int k = 0; k < K; ++k)
+      for (int j = 0; j < R; ++j) {
+        rc[(size_t)k * R + j] = rh[j];
+        zcol[(size_t)k * R + j] = zh[k];
+      }
+    upload(S.rhs, rc, st);
+    upload(zk, zcol, st);
+    alloc_state(1, (int)RC, full, nS, o);
+    seed0 = 0;
   }
 
   // autotuning (outside the timed region; cached per shape in the handle)
@@ -955,7 +977,7 @@ struct Solver {
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     HIPCHK(hipEventRecord(e0, st));
-    init_unit(zk.as<double2>(), seed0);
+    init_unit(zk.as<double2>(), seed0, conv ? zk.as<double2>() : nullptr);
     double kms[SCOCG_K_FAMILIES] = {0};
     int64_t kcount[SCOCG_K_FAMILIES] = {0};
     const int64_t it_main = iterate(o, kms, kcount);
@@ -1297,6 +1319,7 @@ scocg_solve_opts check_opts(const scocg_solve_opts* opts) {
   require(o.shift_chunk == SCOCG_AUTO || o.shift_chunk == 0 || o.shift_chunk == 1 ||
               o.shift_chunk == 4 || o.shift_chunk == 16,
           "shift_chunk must be SCOCG_AUTO, 0, 1, 4 or 16");
+  require(o.conventional == 0 || o.conventional == 1, "conventional must be 0 or 1");
   return o;
 }
 
@@ -1324,7 +1347,9 @@ int run_batch(int n, const scocg_handle* hs, const scocg_problem* pr, scocg_solv
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
   HIPCHK(hipEventRecord(e0, st));
-  for (auto* p : ptr) p->init_unit(p->zk.template as<double2>(), p->seed0);
+  for (auto* p : ptr)
+    p->init_unit(p->zk.template as<double2>(), p->seed0,
+                 p->conv ? p->zk.template as<double2>() : nullptr);
   double kms[SCOCG_K_FAMILIES] = {0};
   int64_t kcount[SCOCG_K_FAMILIES] = {0};
   std::vector<double> done_ms(n, 0.0);

@@ -36,7 +36,8 @@ class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int64), ("init_seed", C.c_int32),
                 ("seed_switch", C.c_int32), ("full", C.c_int32), ("refine", C.c_int32),
                 ("poll_every", C.c_int32), ("use_graph", C.c_int32), ("timing", C.c_int32),
-                ("tile", C.c_int32), ("zchunk", C.c_int32), ("shift_chunk", C.c_int32)]
+                ("tile", C.c_int32), ("zchunk", C.c_int32), ("shift_chunk", C.c_int32),
+                ("conventional", C.c_int32)]
 
 
 class Report(C.Structure):
@@ -126,10 +127,11 @@ def _dev_ptr(t):
 
 
 def _opts(tol, max_iter, init_seed, seed_switch, full, refine, poll_every, use_graph, timing,
-          tile, zchunk, shift_chunk):
+          tile, zchunk, shift_chunk, conventional=False):
     return SolveOpts(float(tol), int(max_iter), int(init_seed), int(bool(seed_switch)),
                      int(bool(full)), int(refine), int(poll_every), int(bool(use_graph)),
-                     int(timing), int(tile), int(zchunk), int(shift_chunk))
+                     int(timing), int(tile), int(zchunk), int(shift_chunk),
+                     int(bool(conventional)))
 
 
 def _new_report(K, R):
@@ -162,14 +164,15 @@ class Handle:
 
     def solve(self, z, rhs_idx, s_idx=None, tol=1e-10, max_iter=100000, init_seed=-1,
               seed_switch=True, full=False, refine=0, poll_every=0, use_graph=False, timing=0,
-              tile=0, zchunk=0, shift_chunk=0):
-        """scocg_solve; returns (rc, report dict with [K, R] arrays)."""
+              tile=0, zchunk=0, shift_chunk=0, conventional=False):
+        """scocg_solve; returns (rc, report dict with [K, R] arrays).  conventional=True runs
+        every (energy, column) pair as its own recurrence (the comparison sweep)."""
         lib = load()
         z = _c(z, np.complex128)
         rhs = _c(rhs_idx, np.int64)
         sp = None if s_idx is None else _c(s_idx, np.int64)
         o = _opts(tol, max_iter, init_seed, seed_switch, full, refine, poll_every, use_graph,
-                  timing, tile, zchunk, shift_chunk)
+                  timing, tile, zchunk, shift_chunk, conventional)
         rep, arrays = _new_report(z.size, rhs.size)
         rc = lib.scocg_solve(self._h, z.size, z.ctypes.data, rhs.size, rhs.ctypes.data,
                              0 if sp is None else sp.size,

@@ -560,3 +560,31 @@ def test_batched_uneven_regions_full_size_capped(dev):
         say(f"region {i} pair ({k},{j}): {r['iters'][k, j]} GPU / {int(it[0])} oracle "
             f"iterations, |dG| {d:.2e}")
         assert d <= (1e-8 + 1e-10) / eta
+
+
+def test_conventional_sweep_matches_shifted_and_oracle(dev):
+    """The conventional sweep (every (energy, column) pair its own recurrence) reaches
+    the same Green's functions as the shifted solve within the resolvent bound, with
+    per-pair iteration counts close to the oracle's conventional COCG and to the
+    shifted solve's freeze iterations (equal in exact arithmetic)."""
+    p = W.tiny_fp64()
+    h = scocg.create_from_problem(p, precision=scocg.FP64)
+    rc_s, rep_s = h.solve(p.z, p.rhs_idx, tol=1e-10, full=True)
+    Gs = h.green_columns()
+    rc_c, rep_c = h.solve(p.z, p.rhs_idx, tol=1e-10, full=True, conventional=True)
+    Gc = h.green_columns()
+    h.destroy()
+    assert rc_s == scocg.OK and rc_c == scocg.OK
+    assert (rep_c["status"] == scocg.PAIR_CONVERGED).all()
+    assert (rep_c["true_resid"] <= 1.1e-10).all()
+    eta = p.z.imag.min()
+    d = np.linalg.norm(Gc - Gs, axis=2)
+    assert (d <= (rep_c["true_resid"] + rep_s["true_resid"]) / eta).all()
+    it_c, it_s = rep_c["iters"], rep_s["iters"]
+    assert (np.abs(it_c - it_s) <= 0.1 * it_s + 5).all(), np.abs(it_c - it_s).max()
+    pairs = [(0, 0), (5, 3), (15, 7), (8, 2)]
+    _, it_o, st_o, _ = oracle.cocg_unit_columns(p, p.z, p.rhs_idx, p.rhs_idx, pairs, tol=1e-10)
+    for (k, j), io in zip(pairs, it_o):
+        assert abs(int(it_c[k, j]) - int(io)) <= 0.1 * io + 5, (k, j, it_c[k, j], io)
+    say(f"conventional: {rep_c['seed_iters']} iterations for the slowest pair, "
+        f"{rep_c['solve_ms']:.1f} ms vs shifted {rep_s['solve_ms']:.1f} ms")
