@@ -202,16 +202,6 @@ __device__ __forceinline__ V csel(bool c, V a, V b) {
   return r;
 }
 
-// *p if ok, else zero.  p must be a valid address either way (callers clamp the
-// index into range), so the load is unconditional and only the value is selected.
-template <typename V>
-__device__ __forceinline__ V ld_or_zero(const V* p, bool ok) {
-  V z;
-  z.x = 0;
-  z.y = 0;
-  return csel(ok, *p, z);
-}
-
 // Streaming accesses that are not re-read by another workgroup (r_{n-1} in, r_{n+1}
 // out): nontemporal, so they do not displace the r_n planes whose halos neighbouring
 // workgroups still read from L2.

@@ -73,6 +73,40 @@ struct DevBuf {
   template <typename U> U* as() const { return static_cast<U*>(p); }
 };
 
+// A HIP event that is destroyed on every path out of its scope (errors throw).
+struct Event {
+  hipEvent_t e = nullptr;
+  Event() { HIPCHK(hipEventCreate(&e)); }
+  Event(const Event&) = delete;
+  Event& operator=(const Event&) = delete;
+  Event(Event&& o) noexcept : e(o.e) { o.e = nullptr; }
+  ~Event() {
+    if (e) (void)hipEventDestroy(e);
+  }
+  operator hipEvent_t() const { return e; }
+};
+
+// device ms between two events recorded on a stream (waits for the second)
+float elapsed_ms(const Event& a, const Event& b) {
+  HIPCHK(hipEventSynchronize(b));
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, a, b));
+  return ms;
+}
+
+// A captured graph and its executable, destroyed on every path out of scope.
+struct Graph {
+  hipGraph_t g = nullptr;
+  hipGraphExec_t x = nullptr;
+  Graph() = default;
+  Graph(const Graph&) = delete;
+  Graph& operator=(const Graph&) = delete;
+  ~Graph() {
+    if (x) (void)hipGraphExecDestroy(x);
+    if (g) (void)hipGraphDestroy(g);
+  }
+};
+
 template <typename U>
 void upload(DevBuf& b, const std::vector<U>& v, hipStream_t s) {
   b.alloc(v.size() * sizeof(U));
@@ -615,20 +649,13 @@ struct Solver {
     ot.use_graph = 0;
     ot.poll_every = iters;
     init_unit(zk, seed0, conv ? zk : nullptr);
-    hipEvent_t a, b;
-    HIPCHK(hipEventCreate(&a));
-    HIPCHK(hipEventCreate(&b));
+    Event a, b;
     HIPCHK(hipEventRecord(a, h.stream));
     double km[SCOCG_K_FAMILIES] = {0};
     int64_t kc[SCOCG_K_FAMILIES] = {0};
     const int64_t n = iterate(ot, km, kc);
     HIPCHK(hipEventRecord(b, h.stream));
-    HIPCHK(hipEventSynchronize(b));
-    float ms = 0.f;
-    HIPCHK(hipEventElapsedTime(&ms, a, b));
-    (void)hipEventDestroy(a);
-    (void)hipEventDestroy(b);
-    return 1e3 * ms / (double)std::max<int64_t>(n, 1);
+    return 1e3 * elapsed_ms(a, b) / (double)std::max<int64_t>(n, 1);
   }
 
   // Autotuning: time each candidate stencil shape (tile x z-chunk), then each shift
@@ -636,10 +663,7 @@ struct Solver {
   double tune(const double2* zk, int seed0, const scocg_solve_opts& o, bool want_tile,
               bool want_zc, bool want_kch) {
     constexpr int kIters = 16;
-    float total = 0.f;
-    hipEvent_t a, b;
-    HIPCHK(hipEventCreate(&a));
-    HIPCHK(hipEventCreate(&b));
+    Event a, b;
     HIPCHK(hipEventRecord(a, h.stream));
     if (want_tile || want_zc) {
       std::vector<int> vs;
@@ -685,11 +709,7 @@ struct Solver {
       S.kch = bk;
     }
     HIPCHK(hipEventRecord(b, h.stream));
-    HIPCHK(hipEventSynchronize(b));
-    HIPCHK(hipEventElapsedTime(&total, a, b));
-    (void)hipEventDestroy(a);
-    (void)hipEventDestroy(b);
-    return total;
+    return elapsed_ms(a, b);
   }
 
   void release_workspace() {
@@ -973,9 +993,7 @@ struct Solver {
     prepare(K, z, R, rhs_idx, nS_in, s_idx, o);
     int tuned_now = 0;
     const double tune_ms = autotune(o, &tuned_now);
-    hipEvent_t e0, e1;
-    HIPCHK(hipEventCreate(&e0));
-    HIPCHK(hipEventCreate(&e1));
+    Event e0, e1;
     HIPCHK(hipEventRecord(e0, st));
     init_unit(zk.as<double2>(), seed0, conv ? zk.as<double2>() : nullptr);
     double kms[SCOCG_K_FAMILIES] = {0};
@@ -984,11 +1002,7 @@ struct Solver {
     std::vector<double> tres;
     const int64_t refined = post(o, it_main, tres);
     HIPCHK(hipEventRecord(e1, st));
-    HIPCHK(hipEventSynchronize(e1));
-    float ms = 0.f;
-    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    const float ms = elapsed_ms(e0, e1);
     return report(o, tres, refined, ms, kms, kcount, tune_ms, tuned_now, rep);
   }
 };
@@ -1151,36 +1165,42 @@ struct Batch {
     int poll = o.poll_every > 0 ? o.poll_every : 16;
     if (poll & 1) ++poll;  // even: the buffer and list parities return to 0 after each poll
     int64_t it = 0;
-    hipGraphExec_t gexec = nullptr;
-    hipGraph_t graph = nullptr;
+    Graph graph;
     // timing: one event pair per kernel family per iteration of a poll chunk
     timing_mode = o.timing;
-    std::vector<hipEvent_t> evs;
-    if (o.timing) {
-      evs.resize((size_t)poll * 2 * SCOCG_K_FAMILIES);
-      for (auto& e : evs) HIPCHK(hipEventCreate(&e));
-    }
-    hipEvent_t evp = nullptr;
-    if (t0 && region_ms) HIPCHK(hipEventCreate(&evp));
+    std::vector<Event> evs;
+    if (o.timing) evs.resize((size_t)poll * 2 * SCOCG_K_FAMILIES);
+    std::vector<hipEvent_t> evh;
+    for (const auto& e : evs) evh.push_back(e);
+    std::unique_ptr<Event> evp;
+    if (t0 && region_ms) evp.reset(new Event());
     std::vector<char> done(sv.size(), 0);
-    auto ev_of = [&](int s2) { return o.timing ? &evs[(size_t)s2 * 2 * SCOCG_K_FAMILIES] : nullptr; };
+    auto ev_of = [&](int s2) { return o.timing ? &evh[(size_t)s2 * 2 * SCOCG_K_FAMILIES] : nullptr; };
     // events recorded during capture cannot be read back after a replay on this
     // runtime: timing runs use direct launches
     const bool use_graph = o.use_graph && !o.timing;
     while (true) {
       if (use_graph) {
-        if (!gexec) {
+        if (!graph.x) {
           HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-          for (int s2 = 0; s2 < poll; ++s2) one_iteration(s2 & 1, ev_of(s2));
-          HIPCHK(hipStreamEndCapture(st, &graph));
-          HIPCHK(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+          try {
+            for (int s2 = 0; s2 < poll; ++s2) one_iteration(s2 & 1, ev_of(s2));
+          } catch (...) {
+            // leave the stream usable: end the capture and drop the partial graph
+            hipGraph_t partial = nullptr;
+            (void)hipStreamEndCapture(st, &partial);
+            if (partial) (void)hipGraphDestroy(partial);
+            throw;
+          }
+          HIPCHK(hipStreamEndCapture(st, &graph.g));
+          HIPCHK(hipGraphInstantiate(&graph.x, graph.g, nullptr, nullptr, 0));
         }
-        HIPCHK(hipGraphLaunch(gexec, st));
+        HIPCHK(hipGraphLaunch(graph.x, st));
       } else {
         for (int s2 = 0; s2 < poll; ++s2) one_iteration(s2 & 1, ev_of(s2));
       }
       it += poll;
-      if (evp) HIPCHK(hipEventRecord(evp, st));
+      if (evp) HIPCHK(hipEventRecord(*evp, st));
       for (SV* p : sv)
         HIPCHK(hipMemcpyAsync(p->S.h_flags, p->S.blk_active.p, p->S.nb * sizeof(int32_t),
                               hipMemcpyDeviceToHost, st));
@@ -1206,7 +1226,7 @@ struct Batch {
           done[r] = 1;
           if (evp) {
             float ms = 0.f;
-            HIPCHK(hipEventElapsedTime(&ms, t0, evp));
+            HIPCHK(hipEventElapsedTime(&ms, t0, *evp));
             region_ms[r] = ms;
           }
         }
@@ -1222,10 +1242,6 @@ struct Batch {
     }
     // every poll chunk ends with an odd-parity iteration (poll is even)
     flush_shift(1);
-    for (auto& e : evs) (void)hipEventDestroy(e);
-    if (evp) (void)hipEventDestroy(evp);
-    if (gexec) (void)hipGraphExecDestroy(gexec);
-    if (graph) (void)hipGraphDestroy(graph);
     return it;
   }
 };
@@ -1343,9 +1359,7 @@ int run_batch(int n, const scocg_handle* hs, const scocg_problem* pr, scocg_solv
     ptr.push_back(sv.back().get());
   }
   hipStream_t st = hs[0]->stream;
-  hipEvent_t e0, e1;
-  HIPCHK(hipEventCreate(&e0));
-  HIPCHK(hipEventCreate(&e1));
+  Event e0, e1;
   HIPCHK(hipEventRecord(e0, st));
   for (auto* p : ptr)
     p->init_unit(p->zk.template as<double2>(), p->seed0,
@@ -1365,18 +1379,11 @@ int run_batch(int n, const scocg_handle* hs, const scocg_problem* pr, scocg_solv
     // refinement, where it runs, extends the region's completion past the loop
     if (!tres[i].empty() && refined[i] > 0) {
       HIPCHK(hipEventRecord(e1, st));
-      HIPCHK(hipEventSynchronize(e1));
-      float t = 0.f;
-      HIPCHK(hipEventElapsedTime(&t, e0, e1));
-      done_ms[i] = t;
+      done_ms[i] = elapsed_ms(e0, e1);
     }
   }
   HIPCHK(hipEventRecord(e1, st));
-  HIPCHK(hipEventSynchronize(e1));
-  float ms = 0.f;
-  HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  const float ms = elapsed_ms(e0, e1);
   int rc = SCOCG_OK;
   for (int i = 0; i < n; ++i) {
     const int r = ptr[i]->report(o, tres[i], refined[i], ms, kms, kcount, 0.0, 0,
