@@ -1,0 +1,88 @@
+"""The synthetic input recipe: every workload has the shapes, counts, windows and
+seeded structure stated for it (grid, atoms, projector support, energies, boundary
+columns), and is reproducible from its seed.  No solver arithmetic is involved."""
+import numpy as np
+import pytest
+
+from paper_1502_00081_amd import workload as W
+
+
+def _planes(p):
+    return p.rhs_idx // (p.nx * p.ny)
+
+
+def _check_common(p, nx, ny, nz, h, K, eta, lo, hi, n_bottom, n_top):
+    assert (p.nx, p.ny, p.nz, p.h) == (nx, ny, nz, h)
+    assert p.vloc.shape == (nx * ny * nz,) and (p.vloc <= 0).all()
+    assert p.z.shape == (K,)
+    np.testing.assert_allclose(p.z.real, np.linspace(lo, hi, K))
+    np.testing.assert_allclose(p.z.imag, eta)
+    pl = _planes(p)
+    assert (pl == 0).sum() == n_bottom and (pl == nz - 1).sum() == n_top
+    assert len(np.unique(p.rhs_idx)) == p.rhs_idx.size
+    # kinetic part: -1/2 of the 9-point second-difference weights / h^2 (nf = 4)
+    c = np.array([float(x) for x in W.FD_SECOND_DERIVATIVE[p.nf]])
+    for axis in range(3):
+        np.testing.assert_allclose(p.coef[axis], -0.5 * c / h ** 2)
+
+
+def test_tiny_and_all_plane_workloads():
+    p = W.tiny_fp64()
+    _check_common(p, 16, 16, 24, 0.4, 16, 1e-3, -0.5, 0.5, 8, 0)
+    assert p.n_atoms == 0 and p.tol == 1e-10
+    q = W.tiny_mixed()
+    _check_common(q, 16, 16, 24, 0.4, 256, 1e-3, -0.5, 0.5, 256, 0)
+    np.testing.assert_array_equal(np.sort(q.rhs_idx), np.arange(256))  # the whole iz = 0 plane
+    np.testing.assert_array_equal(q.vloc, p.vloc)                         # the same H
+
+
+def test_medium_workload():
+    p = W.medium_fp64()
+    _check_common(p, 48, 48, 96, 0.35, 128, 1e-3, -0.6, 0.6, 32, 32)
+    assert p.n_atoms == 40 and p.atom_P.shape[1] == W.N_PROJ
+    # projector support within the cutoff, unit 2-norm channels, D in [-1, 1]
+    sizes = np.diff(p.atom_ptr)
+    assert 300 <= sizes.mean() <= 500
+    for a in range(p.n_atoms):
+        cols = p.atom_P[p.atom_ptr[a]:p.atom_ptr[a + 1]]
+        np.testing.assert_allclose(np.linalg.norm(cols, axis=0), 1.0, rtol=1e-12)
+    assert (np.abs(p.atom_D) <= 1).all()
+    np.testing.assert_array_equal(p.atom_D[:, 1], p.atom_D[:, 2])  # D_p shared by p_x,y,z
+
+
+def test_peapod_geometry():
+    p = W.peapod_large()
+    _check_common(p, 64, 64, 160, 0.4, 512, 5e-4, -0.5, 0.5, 512, 512)
+    assert p.n_atoms == 460
+    c = np.asarray(p.centres)
+    L = 64 * 0.4
+    # the 400 cylinder atoms sit 12.850 bohr from the box axis, up to a periodic image in
+    # x, y (the cylinder is slightly wider than the cell)
+    best = np.full(400, np.inf)
+    for mx in (-1, 0, 1):
+        for my in (-1, 0, 1):
+            r = np.hypot(c[:400, 0] + mx * L - L / 2, c[:400, 1] + my * L - L / 2)
+            best = np.minimum(best, np.abs(r - 12.850))
+    assert best.max() < 1e-9
+    assert (c[:400, 2] >= 0).all() and (c[:400, 2] < 160 * 0.4).all()
+    r_sph = np.linalg.norm(c[400:] - np.array([L / 2, L / 2, 160 * 0.4 / 2]), axis=1)
+    np.testing.assert_allclose(r_sph, 6.614, rtol=1e-12)
+
+
+def test_batched_regions_recipe():
+    regs = W.batched_regions()
+    assert len(regs) == 12
+    for r, p in enumerate(regs):
+        nz = 48 + 16 * r
+        K = 64 + 32 * ((5 * r) % 11)
+        R = 32 * (1 + (7 * r) % 8)
+        _check_common(p, 32, 32, nz, 0.4, K, 1e-3, -0.5, 0.5, R // 2, R // 2)
+        assert p.n_atoms == 0  # no projectors
+    assert sum(p.z.size * p.rhs_idx.size for p in regs) == 401408
+
+
+@pytest.mark.parametrize("name", sorted(W.WORKLOADS))
+def test_workloads_are_reproducible(name):
+    a, b = W.WORKLOADS[name](), W.WORKLOADS[name]()
+    for f in ("vloc", "coef", "z", "rhs_idx", "atom_ptr", "atom_idx", "atom_P", "atom_D"):
+        np.testing.assert_array_equal(getattr(a, f), getattr(b, f))
