@@ -323,6 +323,19 @@ def test_invalid_solve_arguments(dev):
     with pytest.raises(scocg.ScocgError) as e:
         h.solve(p.z, np.array([p.n], np.int64))
     assert e.value.code == scocg.EINVAL
+    for z, rhs, s in ((p.z[:0], p.rhs_idx, None),                 # no energies
+                      (p.z, p.rhs_idx[:0], None),                 # no right-hand sides
+                      (p.z, p.rhs_idx, np.array([-1], np.int64)),  # row out of range
+                      (np.array([0.1 + 1e-3j, np.nan]), p.rhs_idx, None)):
+        with pytest.raises(scocg.ScocgError) as e:
+            h.solve(z, rhs, s_idx=s)
+        assert e.value.code == scocg.EINVAL
+    with pytest.raises(scocg.ScocgError) as e:
+        h.solve(p.z, p.rhs_idx, init_seed=p.z.size)
+    assert e.value.code == scocg.EINVAL
+    # a failed call leaves the handle usable
+    rc, rep = h.solve(p.z, p.rhs_idx, tol=1e-10)
+    assert rc == scocg.OK
     h.destroy()
 
 
