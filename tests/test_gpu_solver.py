@@ -601,3 +601,34 @@ def test_conventional_sweep_matches_shifted_and_oracle(dev):
         assert abs(int(it_c[k, j]) - int(io)) <= 0.1 * io + 5, (k, j, it_c[k, j], io)
     say(f"conventional: {rep_c['seed_iters']} iterations for the slowest pair, "
         f"{rep_c['solve_ms']:.1f} ms vs shifted {rep_s['solve_ms']:.1f} ms")
+
+
+def test_conventional_mixed_refined_and_autotuned_mixed(dev):
+    """complex64 conventional sweep with refinement (per-column energies in the
+    correction solves) certifies every pair and agrees with the FP64 shifted solve;
+    an autotuned complex64 solve gives the default-shape result within the bound."""
+    p = W.tiny_fp64()
+    p = p.with_(z=p.z[::4])
+    tol = 1e-8
+    h64 = scocg.create_from_problem(p, precision=scocg.FP64)
+    rc, rep64 = h64.solve(p.z, p.rhs_idx, tol=1e-11, full=True)
+    G64 = h64.green_columns()
+    h64.destroy()
+    h = scocg.create_from_problem(p, precision=scocg.MIXED)
+    rc, rep = h.solve(p.z, p.rhs_idx, tol=tol, full=True, refine=3, conventional=True)
+    G = h.green_columns()
+    assert rc == scocg.OK and (rep["status"] == scocg.PAIR_CONVERGED).all()
+    assert (rep["true_resid"] <= tol).all()
+    eta = p.z.imag.min()
+    d = np.linalg.norm(G - G64, axis=2)
+    assert (d <= (rep["true_resid"] + rep64["true_resid"]) / eta).all()
+    A = scocg.AUTO
+    rc, ra = h.solve(p.z, p.rhs_idx, tol=tol, full=True, refine=3, tile=A, zchunk=A,
+                     shift_chunk=A)
+    Ga = h.green_columns()
+    h.destroy()
+    say(f"mixed autotuned shape: tile {ra['tile']} zchunk {ra['zchunk']} "
+        f"shift chunk {ra['shift_chunk']}")
+    assert rc == scocg.OK and ra["tuned"]
+    d2 = np.linalg.norm(Ga - G64, axis=2)
+    assert (d2 <= (ra["true_resid"] + rep64["true_resid"]) / eta).all()
