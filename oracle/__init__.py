@@ -10,6 +10,9 @@ Functions (each a thin ctypes marshaller over oracle.c):
   cocg(op, z, b, ...)                conventional COCG, one system       (App., Eqs. A1-A6)
   cocg_unit_columns(op, pairs, ...)  many (z_k, e_j) systems, OpenMP     (Sec. 3B, Eq. 17)
   shifted_cocg(op, z, b, ...)        shifted COCG + seed switching       (App., Eqs. A7-A13)
+The submodule oracle.obm holds the open-boundary reference: perturbed Green's
+function blocks by direct inversion of Eq. 13, the Fisher-Lee transmission
+(Eq. 14) and the density of states.
 """
 from __future__ import annotations
 

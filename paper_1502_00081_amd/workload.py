@@ -186,7 +186,7 @@ def boundary_points(nx, ny, nz, rng, n_bottom, n_top):
         out.append(np.sort(rng.choice(nxy, n_bottom, replace=False)))
     if n_top:
         out.append(np.sort(rng.choice(nxy, n_top, replace=False)) + nxy * (nz - 1))
-    return np.concatenate(out).astype(np.int64)
+    return np.concatenate(out).astype(np.int64) if out else np.zeros(0, np.int64)
 
 
 def make_problem(name, nx, ny, nz, h, nf, n_atoms, projectors, K, eta, elo, ehi,
@@ -278,3 +278,165 @@ WORKLOADS = {
     "tiny_mixed": tiny_mixed,
     "peapod_large": peapod_large,
 }
+
+
+# ---------------------------------------------------------------------------
+# Electrodes: synthetic semi-infinite leads and their self-energies.
+#
+# The perturbed Green's function of the transition region needs the lead
+# self-energies Sigma_L(z_0; Z) and Sigma_R(z_{m+1}; Z) (Sec. 2B, Eqs. 10-11).
+# In the paper they come from the electrode calculation; here they are inputs
+# built for ideal wires: the lead continues the transition region's grid and
+# finite-difference operator along z with a constant potential v_lead and no
+# projectors.  With half-width nf, nf consecutive x-y planes form one principal
+# layer, so the boundary blocks z_0 and z_{m+1} are the first and last nf planes
+# of the region (M = nf*nx*ny rows each, plane-major within the block, i.e. the
+# grid order).
+#
+# Periodic x and y make every transverse Fourier mode q an independent
+# one-dimensional chain of nf x nf layer blocks; the surface Green's function
+# of each chain comes from the decimation iteration of Lopez Sancho, Lopez
+# Sancho and Rubio (J. Phys. F 15, 851 (1985)), and the real-space block is the
+# inverse transverse Fourier transform of the per-mode result.
+# ---------------------------------------------------------------------------
+
+def transverse_energies(nx, ny, coef):
+    """eps(q) = sum_axis [c_0 + 2 sum_d c_d cos(d q)] over the nx*ny transverse modes.
+
+    Returns eps [nx*ny] in the order q = (mx, my) -> mx + nx*my."""
+    nf = coef.shape[1] - 1
+    qx = 2 * np.pi * np.arange(nx) / nx
+    qy = 2 * np.pi * np.arange(ny) / ny
+    ex = coef[0, 0] + 2 * sum(coef[0, d] * np.cos(d * qx) for d in range(1, nf + 1))
+    ey = coef[1, 0] + 2 * sum(coef[1, d] * np.cos(d * qy) for d in range(1, nf + 1))
+    return (ex[None, :] + ey[:, None]).ravel()
+
+
+def lead_layer_blocks(coef):
+    """Layer blocks of the z chain: t00 [nf,nf] (within a layer) and t01 [nf,nf].
+
+    t01[p, q] couples plane p of layer l to plane q of layer l+1, whose distance
+    is nf + q - p; it is nonzero for q <= p."""
+    nf = coef.shape[1] - 1
+    cz = coef[2]
+    t00 = np.zeros((nf, nf))
+    t01 = np.zeros((nf, nf))
+    for p in range(nf):
+        for q in range(nf):
+            t00[p, q] = cz[abs(p - q)]
+            d = nf + q - p
+            if d <= nf:
+                t01[p, q] = cz[d]
+    return t00, t01
+
+
+def _surface_gf(zeta, t00, tc, max_iter=200):
+    """Surface Green's function of a semi-infinite chain, one per row of zeta.
+
+    The chain is layer 0, 1, 2, ... with on-site block t00 + (diagonal shift)
+    and block tc coupling layer l to layer l+1 (its transpose couples back).
+    zeta [nq] holds Z - shift per mode.  Decimation: every pass removes every
+    other layer, squaring the effective coupling."""
+    nf = t00.shape[0]
+    nq = zeta.shape[0]
+    eye = np.eye(nf)
+    a = np.broadcast_to(tc.astype(np.complex128), (nq, nf, nf)).copy()
+    b = np.broadcast_to(tc.T.astype(np.complex128), (nq, nf, nf)).copy()
+    es = np.broadcast_to(t00.astype(np.complex128), (nq, nf, nf)).copy()
+    e = es.copy()
+    zI = zeta[:, None, None] * eye
+    scale = max(1.0, float(np.abs(tc).max()))
+    for _ in range(max_iter):
+        g = np.linalg.inv(zI - e)
+        ag = a @ g
+        bg = b @ g
+        agb = ag @ b
+        es = es + agb
+        e = e + agb + bg @ a
+        a = ag @ a
+        b = bg @ b
+        if max(np.abs(a).max(), np.abs(b).max()) < 1e-15 * scale:
+            break
+    else:
+        raise RuntimeError("lead decimation did not converge (Im Z too small?)")
+    return np.linalg.inv(zI - es)
+
+
+def lead_self_energies(nx, ny, coef, z, v_lead=0.0):
+    """Sigma_L(z_0; Z_k), Sigma_R(z_{m+1}; Z_k) for ideal leads, [K, M, M] each.
+
+    Row/column order inside a block: xy + nx*ny*p for plane p = 0..nf-1 of the
+    block (grid order).  Both are complex symmetric.  Sigma_R = t01 g_R t01^T
+    with g_R the surface block of the right lead (extending to +z);
+    Sigma_L = t01^T g_L t01 with g_L that of the left lead (extending to -z)."""
+    nf = coef.shape[1] - 1
+    nxy = nx * ny
+    t00, t01 = lead_layer_blocks(coef)
+    eps = transverse_energies(nx, ny, coef)
+    ix = np.arange(nx)
+    iy = np.arange(ny)
+    rx = (ix[None, :] + 0 * iy[:, None]).ravel()
+    ry = (0 * ix[None, :] + iy[:, None]).ravel()
+    qx = 2 * np.pi * (np.arange(nxy) % nx) / nx
+    qy = 2 * np.pi * (np.arange(nxy) // nx) / ny
+    # F[r, q] = exp(i q.r) / sqrt(nxy): unitary transverse Fourier basis
+    F = np.exp(1j * (rx[:, None] * qx[None, :] + ry[:, None] * qy[None, :])) / np.sqrt(nxy)
+    z = np.atleast_1d(np.asarray(z, np.complex128))
+    M = nf * nxy
+    sig_l = np.empty((z.size, M, M), np.complex128)
+    sig_r = np.empty((z.size, M, M), np.complex128)
+    for k, zk in enumerate(z):
+        zeta = zk - eps - v_lead
+        gR = _surface_gf(zeta, t00, t01)
+        gL = _surface_gf(zeta, t00, t01.T)
+        sR = t01 @ gR @ t01.T        # [nq, nf, nf]
+        sL = t01.T @ gL @ t01
+        for out, s in ((sig_r, sR), (sig_l, sL)):
+            # block (p, p') = F diag_q(s[q, p, p']) F^H
+            for p in range(nf):
+                for pp in range(nf):
+                    out[k, p * nxy:(p + 1) * nxy, pp * nxy:(pp + 1) * nxy] = \
+                        (F * s[:, p, pp][None, :]) @ F.conj().T
+    return sig_l, sig_r
+
+
+def obm_indices(nx, ny, nz, nf, extra=None):
+    """Grid indices of the left boundary block (planes 0..nf-1), the right block
+    (planes nz-nf..nz-1) and optional extra rows, in that order."""
+    nxy = nx * ny
+    M = nf * nxy
+    n = nxy * nz
+    if nz < 2 * nf:
+        raise ValueError("the two boundary blocks overlap: need nz >= 2*nf")
+    parts = [np.arange(M), np.arange(n - M, n)]
+    if extra is not None and len(extra):
+        parts.append(np.asarray(extra, np.int64))
+    return np.concatenate(parts).astype(np.int64)
+
+
+def interior_centres(nx, ny, nz, h, nf, n_atoms, rng, margin=1.5):
+    """Atom centres kept at least `margin` bohr away from the two boundary blocks."""
+    zlo = nf * h + margin
+    zhi = (nz - nf - 1) * h - margin
+    return np.stack([rng.uniform(0, nx * h, n_atoms), rng.uniform(0, ny * h, n_atoms),
+                     rng.uniform(zlo, zhi, n_atoms)], axis=1)
+
+
+def obm_wire(nx=8, ny=8, nz=32, h=0.4, n_atoms=4, K=16, eta=1e-3, elo=0.1, ehi=3.0, seed=1502 + 7,
+             projectors=True, extra_plane=True, tol=1e-10):
+    """Scatterer between two ideal V=0 leads for the open-boundary matching.
+
+    8x8x32 grid (2048 points), h=0.4, nf=4; n_atoms Gaussians with projectors
+    away from the boundary blocks; K energies in [0.1, 3.0] Ha (one to five
+    open lead channels), eta=1e-3.  RHS set = rows = left block (256), right
+    block (256) and, for the density of states, the middle plane (64).
+    Returns (problem, M, L)."""
+    rng = np.random.default_rng(seed)
+    nf = 4
+    centres = interior_centres(nx, ny, nz, h, nf, n_atoms, rng) if n_atoms else np.zeros((0, 3))
+    p = make_problem(f"obm_wire_{nx}x{ny}x{nz}", nx, ny, nz, h, nf, 0, projectors, K, eta,
+                     elo, ehi, 0, 0, seed, tol=tol, centres=centres)
+    nxy = nx * ny
+    extra = np.arange(nxy) + nxy * (nz // 2) if extra_plane else None
+    idx = obm_indices(nx, ny, nz, nf, extra)
+    return p.with_(rhs_idx=idx, s_idx=None), nf * nxy, (nxy if extra_plane else 0)

@@ -86,3 +86,26 @@ def test_workloads_are_reproducible(name):
     a, b = W.WORKLOADS[name](), W.WORKLOADS[name]()
     for f in ("vloc", "coef", "z", "rhs_idx", "atom_ptr", "atom_idx", "atom_P", "atom_D"):
         np.testing.assert_array_equal(getattr(a, f), getattr(b, f))
+
+
+def test_obm_wire_index_sets_and_atoms_clear_of_the_boundary_blocks():
+    """Left block = planes 0..nf-1, right block = last nf planes, extra = middle plane;
+    every atom's projector support stays outside both boundary blocks."""
+    p, M, L = W.obm_wire()
+    nxy = p.nx * p.ny
+    assert M == p.nf * nxy and L == nxy
+    idx = p.rhs_idx
+    assert idx.size == 2 * M + L and np.unique(idx).size == idx.size
+    assert np.array_equal(idx[:M], np.arange(M))
+    assert np.array_equal(idx[M:2 * M], np.arange(p.n - M, p.n))
+    assert np.all(idx[2 * M:] // nxy == p.nz // 2)
+    planes = p.atom_idx // nxy
+    assert planes.min() >= p.nf and planes.max() < p.nz - p.nf
+    sl, sr = W.lead_self_energies(p.nx, p.ny, p.coef, p.z[:2])
+    assert sl.shape == (2, M, M) and sr.shape == (2, M, M)
+    # complex symmetric, and -Im Sigma is positive semi-definite (a retarded self-energy)
+    for s in (sl, sr):
+        assert np.abs(s - s.transpose(0, 2, 1)).max() < 1e-12 * np.abs(s).max()
+        for k in range(2):
+            g = 1j * (s[k] - s[k].conj().T)
+            assert np.linalg.eigvalsh(g).min() > -1e-10
