@@ -218,13 +218,59 @@ int scocg_batch_solve(int32_t n, const scocg_handle *hs, const scocg_problem *pr
 /*
  * Copy the last solve's x^{(k)}_j[S] into dst, layout [K][R][nS] (row-major),
  * element SCOCG_C128 (2 doubles) or SCOCG_C64 (2 floats).  dst is a device
- * pointer (dst_is_device = 1, on the handle's device) or host memory.
+ * pointer (dst_is_device = 1, on the handle's device, inside one allocation of
+ * at least K R nS elements, else SCOCG_EINVAL) or host memory.
  * Enqueued on the handle's stream; returns after the copy completes.
  */
 int scocg_green_columns(scocg_handle h, void *dst, int32_t dtype, int32_t dst_is_device);
 
 /* Apply y = H x for complex128 device vectors x, y of length N (checking aid). */
 int scocg_apply_h(scocg_handle h, const void *x_dev, void *y_dev);
+
+/*
+ * Open-boundary matching (Sec. 3B, Eqs. 18-24) and transmission (Sec. 2B, Eq. 14).
+ *
+ * From the unperturbed Green's function of the isolated transition region on an
+ * index list idx = (left block, right block, extra rows) -- the left block being
+ * the M rows nearest the left lead (the first principal layer z_0: for half-width
+ * nf the first nf x-y planes), the right block the M rows nearest the right lead
+ * (z_{m+1}), then L rows anywhere (e.g. a plane whose local density of states is
+ * wanted, Sec. 3B after Eq. 24) -- and the two lead self-energies, compute for
+ * every energy Z_k:
+ *   - the perturbed Green's function G_T(Z_k) on idx x idx: the inverse of Eq. 13
+ *     restricted to idx, obtained from Eq. 18 on the boundary rows,
+ *         (I - G_bb Sigma_b) G_T(b, :) = G(b, :),  Sigma_b = diag(Sigma_L, Sigma_R),
+ *     solved as one 2M x 2M system (the block elimination of Eqs. 19-24 done by
+ *     Gauss-Jordan elimination with partial pivoting), and on the extra rows
+ *         G_T(l, :) = G(l, :) + G(l, b) Sigma_b G_T(b, :);
+ *   - the Fisher-Lee transmission T = Tr[Gamma_L G^a(z_0, z_{m+1}) Gamma_R
+ *     G^r(z_{m+1}, z_0)] with Gamma = i (Sigma - Sigma^dagger) (Eqs. 14-16), taking
+ *     G^r = G_T(Z_k) and G^a its conjugate transpose;
+ *   - the density of states of the extra rows, -Im tr G_T(l, l) / pi.
+ *
+ * Arguments (all matrices complex128, column-major per energy: element (r, c) at
+ * r + ld * c; device pointers are on the handle's device and must lie inside one
+ * allocation, else SCOCG_EINVAL):
+ *   K          energies, 1..16383.
+ *   M          rows per boundary block (>= 1); L extra rows (>= 0); D = 2M + L.
+ *   g_dev      [K][D][D] device: G(Z_k)[idx_r, idx_c] at r + D c -- the layout that
+ *              scocg_green_columns writes after scocg_solve with rhs_idx = idx and
+ *              S = the RHS set (G is complex symmetric, so rows and columns agree).
+ *   sig_l_dev  [K][M][M] device: Sigma_L(z_0; Z_k) on the left block's rows.
+ *   sig_r_dev  [K][M][M] device: Sigma_R(z_{m+1}; Z_k) on the right block's rows.
+ *   gt_dev     [K][D][D] device output, G_T on idx x idx (same layout), or NULL; it
+ *              may not overlap an input.
+ *   trans      [K][2] host output (re, im of T; im vanishes up to rounding) or NULL.
+ *   dos        [K] host output or NULL (0 when L = 0).
+ * Work runs on the handle's stream; the call returns after it completes.  The
+ * handle's operator and last solve are not used or changed.  Device workspace of
+ * about 16 K (2M (2M + D) + 3 M^2 + 2 L M) bytes is allocated for the call.
+ * Returns SCOCG_BREAKDOWN (outputs of the affected energies NaN) if the 2M x 2M
+ * system of an energy meets a zero pivot.
+ */
+int scocg_obm(scocg_handle h, int32_t K, int32_t M, int32_t L, const void *g_dev,
+              const void *sig_l_dev, const void *sig_r_dev, void *gt_dev, double *trans,
+              double *dos);
 
 /* Release every device buffer of the handle.  NULL is ignored. */
 void scocg_destroy(scocg_handle h);

@@ -1,0 +1,319 @@
+// Device kernels of the open-boundary matching step (Sec. 3B, Eqs. 18-24) and
+// of the Fisher-Lee transmission (Sec. 2B, Eqs. 14-16).
+//
+// Inputs per energy Z_k: the unperturbed Green's function on an index list
+// (left boundary block, right boundary block, optional extra rows), stored
+// column-major as the solver writes it, and the two lead self-energies.  With
+// b = both boundary blocks (n = 2M rows) and Sigma_b = diag(Sigma_L, Sigma_R),
+// the perturbed function on the boundary rows solves
+//     (I - G_bb Sigma_b) G_T(b, :) = G(b, :)                        (Eq. 18 on rows b)
+// and the extra rows follow as
+//     G_T(l, :) = G(l, :) + G(l, b) Sigma_b G_T(b, :).               (Eq. 18 on rows l)
+// Eqs. 19-24 are the two-by-two block elimination of the first system; here it
+// is solved as one n x n system by Gauss-Jordan elimination with partial
+// pivoting, one pivot per launch pair, all energies in one grid.
+//
+// Every matrix is complex128 (double2: re, im), column-major: element (r, c)
+// of a matrix with leading dimension ld is at r + ld * c.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace scocg {
+namespace obm {
+
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return {a.x + b.x, a.y + b.y}; }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return {a.x - b.x, a.y - b.y}; }
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return {fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x)};
+}
+__device__ __forceinline__ double2 cconj(double2 a) { return {a.x, -a.y}; }
+// acc += a * b
+__device__ __forceinline__ void cfma(double2& acc, double2 a, double2 b) {
+  acc.x = fma(a.x, b.x, fma(-a.y, b.y, acc.x));
+  acc.y = fma(a.x, b.y, fma(a.y, b.x, acc.y));
+}
+__device__ __forceinline__ double cabs2(double2 a) { return a.x * a.x + a.y * a.y; }
+
+// One product of a batch: C = beta C + alpha op(A) B.
+struct GemmPtrs {
+  const double2* A;
+  const double2* B;
+  double2* C;
+};
+
+constexpr int GT = 64;   // output tile (rows and columns)
+constexpr int GKC = 16;  // contraction chunk staged in LDS
+
+// Batched complex GEMM, 256 threads, a 64 x 64 output tile per workgroup and
+// 4 x 4 outputs per thread.  op(A) = A (m x k, leading dimension lda) or, with
+// CONJ_A, A^H where A is stored k x m.  B is k x n (ldb), C is m x n (ldc).
+// beta_zero skips the read of C (it may hold anything).  grid.z = batch entry.
+template <bool CONJ_A>
+__global__ __launch_bounds__(256) void k_zgemm(const GemmPtrs* __restrict__ list, int m, int n,
+                                               int kdim, int lda, int ldb, int ldc, double2 alpha,
+                                               double2 beta, int beta_zero) {
+  const GemmPtrs g = list[blockIdx.z];
+  __shared__ double2 As[GKC][GT + 1];
+  __shared__ double2 Bs[GKC][GT + 1];
+  const int tid = threadIdx.x;
+  const int tx = tid & 15, ty = tid >> 4;
+  const int r0 = blockIdx.x * GT, c0 = blockIdx.y * GT;
+  double2 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = {0.0, 0.0};
+
+  for (int k0 = 0; k0 < kdim; k0 += GKC) {
+#pragma unroll
+    for (int e = tid; e < GT * GKC; e += 256) {
+      int row, kk;
+      if (CONJ_A) {
+        kk = e & (GKC - 1);
+        row = e / GKC;
+      } else {
+        row = e & (GT - 1);
+        kk = e / GT;
+      }
+      const int gr = r0 + row, gk = k0 + kk;
+      double2 v = {0.0, 0.0};
+      if (gr < m && gk < kdim)
+        v = CONJ_A ? cconj(g.A[gk + (size_t)lda * gr]) : g.A[gr + (size_t)lda * gk];
+      As[kk][row] = v;
+    }
+#pragma unroll
+    for (int e = tid; e < GT * GKC; e += 256) {
+      const int kk = e & (GKC - 1), col = e / GKC;
+      const int gk = k0 + kk, gc = c0 + col;
+      double2 v = {0.0, 0.0};
+      if (gk < kdim && gc < n) v = g.B[gk + (size_t)ldb * gc];
+      Bs[kk][col] = v;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < GKC; ++kk) {
+      double2 a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = As[kk][tx + 16 * i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][ty + 16 * j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) cfma(acc[i][j], a[i], b[j]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int c = c0 + ty + 16 * j;
+    if (c >= n) continue;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = r0 + tx + 16 * i;
+      if (r >= m) continue;
+      double2* dst = g.C + r + (size_t)ldc * c;
+      double2 v = cmul(alpha, acc[i][j]);
+      if (!beta_zero) v = cadd(v, cmul(beta, *dst));
+      *dst = v;
+    }
+  }
+}
+
+// W_k = [ I_n | G_k(0:n, 0:D) ]: the augmented system of energy k, n x (n + D),
+// leading dimension n.  g is [K][D][D] (column-major per energy).
+// grid = (columns of W, row chunks, energies) here and in k_obm_out, k_gamma.
+__global__ __launch_bounds__(256) void k_obm_init(const double2* __restrict__ g, double2* W,
+                                                  int n, int D) {
+  const int k = blockIdx.z;
+  const int c = blockIdx.x;  // column of W, 0 .. n + D - 1
+  const double2* gk = g + (size_t)k * D * D;
+  double2* Wc = W + (size_t)k * n * (n + D) + (size_t)n * c;
+  for (int i = blockIdx.y * 256 + threadIdx.x; i < n; i += gridDim.y * 256) {
+    double2 v;
+    if (c < n)
+      v = {i == c ? 1.0 : 0.0, 0.0};
+    else
+      v = gk[i + (size_t)D * (c - n)];
+    Wc[i] = v;
+  }
+}
+
+// Pivot step j of Gauss-Jordan elimination on W_k (one workgroup per energy):
+// pick p = argmax_{i >= j} |W(i, j)| (the smallest such i on ties), swap rows p
+// and j over columns j.., scale row j by 1 / W(j, j), and store the multipliers
+// f(i) = W(i, j) for i != j (f(j) = 0).  A zero or non-finite pivot marks the
+// energy failed; its later steps are skipped.
+__global__ __launch_bounds__(256) void k_gj_pivot(double2* W, double2* f, int32_t* fail, int n,
+                                                  int ncol, int j) {
+  const int k = blockIdx.x;
+  if (fail[k]) return;
+  double2* Wk = W + (size_t)k * n * ncol;
+  double2* fk = f + (size_t)k * n;
+  __shared__ double s_val[256];
+  __shared__ int s_idx[256];
+  const int tid = threadIdx.x;
+  double best = -1.0;
+  int bi = n;
+  for (int i = j + tid; i < n; i += 256) {
+    const double a = cabs2(Wk[i + (size_t)n * j]);
+    if (a > best) {  // strict: keeps the smallest index within the thread
+      best = a;
+      bi = i;
+    }
+  }
+  s_val[tid] = best;
+  s_idx[tid] = bi;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (tid < s) {
+      const double o = s_val[tid + s];
+      const int oi = s_idx[tid + s];
+      if (o > s_val[tid] || (o == s_val[tid] && oi < s_idx[tid])) {
+        s_val[tid] = o;
+        s_idx[tid] = oi;
+      }
+    }
+    __syncthreads();
+  }
+  const int p = s_idx[0];
+  const double pv = s_val[0];
+  if (!(pv > 0.0) || !isfinite(pv) || p >= n) {
+    if (tid == 0) fail[k] = 1;
+    return;
+  }
+  if (p != j) {
+    for (int c = j + tid; c < ncol; c += 256) {
+      double2* a = Wk + j + (size_t)n * c;
+      double2* b = Wk + p + (size_t)n * c;
+      const double2 t = *a;
+      *a = *b;
+      *b = t;
+    }
+  }
+  __syncthreads();
+  const double2 piv = Wk[j + (size_t)n * j];
+  const double inv_den = 1.0 / cabs2(piv);
+  const double2 inv = {piv.x * inv_den, -piv.y * inv_den};
+  for (int i = tid; i < n; i += 256) fk[i] = (i == j) ? double2{0.0, 0.0} : Wk[i + (size_t)n * j];
+  __syncthreads();  // column j read before row j is rescaled
+  for (int c = j + tid; c < ncol; c += 256) {
+    double2* a = Wk + j + (size_t)n * c;
+    *a = cmul(*a, inv);
+  }
+}
+
+constexpr int GJ_COLS = 8;  // columns per thread in the elimination update
+
+// Elimination step j: W(i, c) -= f(i) W(j, c) for every row i != j (f(j) = 0)
+// and every column c > j.  grid = (row tiles of 256, column groups, energies).
+__global__ __launch_bounds__(256) void k_gj_elim(double2* W, const double2* __restrict__ f,
+                                                 const int32_t* __restrict__ fail, int n, int ncol,
+                                                 int j) {
+  const int k = blockIdx.z;
+  if (fail[k]) return;
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const int cbeg = j + 1 + blockIdx.y * GJ_COLS;
+  if (i >= n || cbeg >= ncol) return;
+  double2* Wk = W + (size_t)k * n * ncol;
+  const double2 fi = f[(size_t)k * n + i];
+  if (fi.x == 0.0 && fi.y == 0.0) return;
+  const int cend = min(cbeg + GJ_COLS, ncol);
+  for (int c = cbeg; c < cend; ++c) {
+    const double2 pj = Wk[j + (size_t)n * c];
+    double2* a = Wk + i + (size_t)n * c;
+    double2 v = *a;
+    v.x = fma(-fi.x, pj.x, fma(fi.y, pj.y, v.x));
+    v.y = fma(-fi.x, pj.y, fma(-fi.y, pj.x, v.y));
+    *a = v;
+  }
+}
+
+// G_T rows: rows 0..n-1 from the solved system (W columns n..n+D-1), rows
+// n..D-1 start as the unperturbed rows (the extra-row update adds to them).
+__global__ __launch_bounds__(256) void k_obm_out(const double2* __restrict__ W,
+                                                 const double2* __restrict__ g, double2* gt, int n,
+                                                 int D) {
+  const int k = blockIdx.z;
+  const int c = blockIdx.x;
+  const double2* Wk = W + (size_t)k * n * (n + D) + (size_t)n * (n + c);
+  const double2* gk = g + (size_t)k * D * D + (size_t)D * c;
+  double2* out = gt + (size_t)k * D * D + (size_t)D * c;
+  for (int i = blockIdx.y * 256 + threadIdx.x; i < D; i += gridDim.y * 256)
+    out[i] = i < n ? Wk[i] : gk[i];
+}
+
+// Gamma = i (Sigma - Sigma^H) (Eq. 16), M x M per energy.
+__global__ __launch_bounds__(256) void k_gamma(const double2* __restrict__ sig, double2* gam,
+                                               int M) {
+  const int k = blockIdx.z;
+  const int c = blockIdx.x;
+  const double2* s = sig + (size_t)k * M * M;
+  double2* o = gam + (size_t)k * M * M + (size_t)M * c;
+  for (int r = blockIdx.y * 256 + threadIdx.x; r < M; r += gridDim.y * 256) {
+    const double2 a = s[r + (size_t)M * c];
+    const double2 b = s[c + (size_t)M * r];
+    // i * (a - conj(b))
+    const double2 d = {a.x - b.x, a.y + b.y};
+    o[r] = {-d.y, d.x};
+  }
+}
+
+// T_k = sum_{a, c} Gamma_L(a, c) Q(c, a) with Q = Y^H Gamma_R Y and
+// Y = G_T(right block, left block): the trace of Eq. 14.  Gamma_L is formed on
+// the fly from Sigma_L.  One workgroup per energy, fixed summation order.
+__global__ __launch_bounds__(256) void k_trace_gamma(const double2* __restrict__ sig_l,
+                                                     const double2* __restrict__ Q, double2* T,
+                                                     const int32_t* __restrict__ fail, int M) {
+  const int k = blockIdx.x;
+  const double2* s = sig_l + (size_t)k * M * M;
+  const double2* q = Q + (size_t)k * M * M;
+  __shared__ double sx[256], sy[256];
+  const int tid = threadIdx.x;
+  double2 acc = {0.0, 0.0};
+  const int64_t MM = (int64_t)M * M;
+  for (int64_t e = tid; e < MM; e += 256) {
+    const int a = (int)(e % M), c = (int)(e / M);
+    const double2 sa = s[a + (size_t)M * c];
+    const double2 sb = s[c + (size_t)M * a];
+    const double2 d = {sa.x - sb.x, sa.y + sb.y};
+    const double2 gl = {-d.y, d.x};
+    cfma(acc, gl, q[c + (size_t)M * a]);
+  }
+  sx[tid] = acc.x;
+  sy[tid] = acc.y;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (tid < st) {
+      sx[tid] += sx[tid + st];
+      sy[tid] += sy[tid + st];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) T[k] = fail[k] ? double2{NAN, NAN} : double2{sx[0], sy[0]};
+}
+
+// DOS_k = -Im sum_{i < L} G_T(n + i, n + i) / pi over the extra rows.
+__global__ __launch_bounds__(256) void k_dos(const double2* __restrict__ gt, double* dos,
+                                             const int32_t* __restrict__ fail, int n, int D,
+                                             int L) {
+  const int k = blockIdx.x;
+  const double2* gk = gt + (size_t)k * D * D;
+  __shared__ double sy[256];
+  const int tid = threadIdx.x;
+  double acc = 0.0;
+  for (int i = tid; i < L; i += 256) acc += gk[(n + i) + (size_t)D * (n + i)].y;
+  sy[tid] = acc;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (tid < st) sy[tid] += sy[tid + st];
+    __syncthreads();
+  }
+  if (tid == 0) dos[k] = fail[k] ? NAN : -sy[0] / M_PI;
+}
+
+}  // namespace obm
+}  // namespace scocg

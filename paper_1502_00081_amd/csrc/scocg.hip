@@ -25,6 +25,7 @@
 #include <vector>
 
 #include "kernels.hpp"
+#include "obm_kernels.hpp"
 #include "scocg.h"
 
 using namespace scocg;
@@ -1297,6 +1298,148 @@ int guarded(F&& f) {
   }
 }
 
+
+// [p, p + bytes) must lie inside one device allocation of `device`: a host or
+// foreign pointer, or a buffer too small for the shape, is an argument error
+// here rather than a memory fault inside a kernel.
+void require_device_range(const void* p, size_t bytes, int device, const char* name) {
+  require(p != nullptr, std::string(name) + " is NULL");
+  hipPointerAttribute_t at{};
+  if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+    (void)hipGetLastError();
+    require(false, std::string(name) + " is not device memory");
+  }
+  require(at.type == hipMemoryTypeDevice && at.device == device,
+          std::string(name) + " is not device memory of the handle's device");
+  void* base = nullptr;
+  size_t size = 0;
+  if (hipMemGetAddressRange(&base, &size, const_cast<void*>(p)) != hipSuccess) {
+    (void)hipGetLastError();
+    require(false, std::string(name) + ": allocation range unknown");
+  }
+  require(static_cast<const char*>(p) + bytes <= static_cast<const char*>(base) + size,
+          std::string(name) + " is smaller than the shape requires");
+}
+
+// Open-boundary matching on the device (see obm_kernels.hpp) for K energies,
+// boundary blocks of M rows each and L extra rows; D = 2M + L, n = 2M.
+//   g [K][D][D], sig_l, sig_r [K][M][M] inputs; gt [K][D][D] output (device).
+//   T [K] complex transmission, dos [K] (device scratch, copied out by the caller).
+// Returns the number of energies whose elimination met a zero pivot.
+int obm_run(scocg_ctx& h, int K, int M, int L, const double2* g, const double2* sig_l,
+            const double2* sig_r, double2* gt, std::vector<double2>& T_host,
+            std::vector<double>& dos_host) {
+  hipStream_t st = h.stream;
+  const int n = 2 * M, D = 2 * M + L, ncol = n + D;
+  DevBuf W, f, fail, P, GR, U, Q, T, dos, lists;
+  W.alloc(sizeof(double2) * (size_t)K * n * ncol);
+  f.alloc(sizeof(double2) * (size_t)K * n);
+  fail.alloc(sizeof(int32_t) * K);
+  GR.alloc(sizeof(double2) * (size_t)K * M * M);
+  U.alloc(sizeof(double2) * (size_t)K * M * M);
+  Q.alloc(sizeof(double2) * (size_t)K * M * M);
+  T.alloc(sizeof(double2) * K);
+  dos.alloc(sizeof(double) * K);
+  if (L > 0) P.alloc(sizeof(double2) * (size_t)K * L * n);
+  double2* Wp = W.as<double2>();
+  const size_t Wstride = (size_t)n * ncol, gstride = (size_t)D * D, sstride = (size_t)M * M;
+  const size_t Pstride = (size_t)L * n;
+
+  // pointer lists of every batched product, uploaded once
+  std::vector<obm::GemmPtrs> hl;
+  const size_t o_build = hl.size();  // W(b_r, b_c) -= G(b_r, b_c) Sigma_c
+  for (int k = 0; k < K; ++k)
+    for (int c = 0; c < 2; ++c)
+      for (int r = 0; r < 2; ++r)
+        hl.push_back({g + k * gstride + (size_t)r * M + (size_t)D * c * M,
+                      (c == 0 ? sig_l : sig_r) + k * sstride,
+                      Wp + k * Wstride + (size_t)r * M + (size_t)n * c * M});
+  const size_t o_p = hl.size();  // P(:, c-block) = G(l, b_c) Sigma_c
+  if (L > 0)
+    for (int k = 0; k < K; ++k)
+      for (int c = 0; c < 2; ++c)
+        hl.push_back({g + k * gstride + n + (size_t)D * c * M,
+                      (c == 0 ? sig_l : sig_r) + k * sstride,
+                      P.as<double2>() + k * Pstride + (size_t)L * c * M});
+  const size_t o_px = hl.size();  // G_T(l, :) += P X
+  if (L > 0)
+    for (int k = 0; k < K; ++k)
+      hl.push_back({P.as<double2>() + k * Pstride, Wp + k * Wstride + (size_t)n * n,
+                    gt + k * gstride + n});
+  const size_t o_u = hl.size();  // U = Gamma_R Y, Y = X(right rows, left columns)
+  for (int k = 0; k < K; ++k)
+    hl.push_back({GR.as<double2>() + k * sstride, Wp + k * Wstride + (size_t)n * n + M,
+                  U.as<double2>() + k * sstride});
+  const size_t o_q = hl.size();  // Q = Y^H U
+  for (int k = 0; k < K; ++k)
+    hl.push_back({Wp + k * Wstride + (size_t)n * n + M, U.as<double2>() + k * sstride,
+                  Q.as<double2>() + k * sstride});
+  lists.alloc(sizeof(obm::GemmPtrs) * hl.size());
+  HIPCHK(hipMemcpyAsync(lists.p, hl.data(), lists.bytes, hipMemcpyHostToDevice, st));
+  const obm::GemmPtrs* dl = lists.as<obm::GemmPtrs>();
+  auto gemm = [&](size_t off, int batch, bool conj_a, int m, int nn, int kd, int lda, int ldb,
+                  int ldc, double2 alpha, double2 beta, int beta_zero) {
+    dim3 grid(nblocks(m, obm::GT), nblocks(nn, obm::GT), batch);
+    if (conj_a)
+      hipLaunchKernelGGL(obm::k_zgemm<true>, grid, dim3(256), 0, st, dl + off, m, nn, kd, lda,
+                         ldb, ldc, alpha, beta, beta_zero);
+    else
+      hipLaunchKernelGGL(obm::k_zgemm<false>, grid, dim3(256), 0, st, dl + off, m, nn, kd, lda,
+                         ldb, ldc, alpha, beta, beta_zero);
+    KCHK();
+  };
+  const double2 one = {1.0, 0.0}, mone = {-1.0, 0.0}, zero = {0.0, 0.0};
+
+  // 1. W = [I | G(b, :)], then W(:, 0:n) -= G_bb Sigma_b
+  HIPCHK(hipMemsetAsync(fail.p, 0, fail.bytes, st));
+  hipLaunchKernelGGL(obm::k_obm_init, dim3(ncol, nblocks(n, 256), K), dim3(256), 0, st, g, Wp,
+                     n, D);
+  KCHK();
+  gemm(o_build, 4 * K, false, M, M, M, D, M, n, mone, one, 0);
+  // 2. Gauss-Jordan: W(:, n:) becomes G_T(b, :)
+  for (int j = 0; j < n; ++j) {
+    hipLaunchKernelGGL(obm::k_gj_pivot, dim3(K), dim3(256), 0, st, Wp, f.as<double2>(),
+                       fail.as<int32_t>(), n, ncol, j);
+    KCHK();
+    const int cols = ncol - j - 1;
+    if (cols > 0) {
+      hipLaunchKernelGGL(obm::k_gj_elim, dim3(nblocks(n, 256), nblocks(cols, obm::GJ_COLS), K),
+                         dim3(256), 0, st, Wp, f.as<double2>(), fail.as<int32_t>(), n, ncol, j);
+      KCHK();
+    }
+  }
+  // 3. output rows: boundary rows from X, extra rows G(l, :) + G(l, b) Sigma_b X
+  hipLaunchKernelGGL(obm::k_obm_out, dim3(D, nblocks(D, 256), K), dim3(256), 0, st, Wp, g, gt, n,
+                     D);
+  KCHK();
+  if (L > 0) {
+    gemm(o_p, 2 * K, false, L, M, M, D, M, L, one, zero, 1);
+    gemm(o_px, K, false, L, D, n, L, n, D, one, one, 0);
+  }
+  // 4. T = Tr[Gamma_L Y^H Gamma_R Y]
+  hipLaunchKernelGGL(obm::k_gamma, dim3(M, nblocks(M, 256), K), dim3(256), 0, st, sig_r,
+                     GR.as<double2>(), M);
+  KCHK();
+  gemm(o_u, K, false, M, M, M, M, n, M, one, zero, 1);
+  gemm(o_q, K, true, M, M, M, n, M, M, one, zero, 1);
+  hipLaunchKernelGGL(obm::k_trace_gamma, dim3(K), dim3(256), 0, st, sig_l, Q.as<double2>(),
+                     T.as<double2>(), fail.as<int32_t>(), M);
+  KCHK();
+  hipLaunchKernelGGL(obm::k_dos, dim3(K), dim3(256), 0, st, gt, dos.as<double>(),
+                     fail.as<int32_t>(), n, D, L);
+  KCHK();
+  std::vector<int32_t> fl(K);
+  T_host.resize(K);
+  dos_host.resize(K);
+  HIPCHK(hipMemcpyAsync(T_host.data(), T.p, T.bytes, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(dos_host.data(), dos.p, dos.bytes, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(fl.data(), fail.p, fail.bytes, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));  // every workspace buffer is freed on return
+  int nfail = 0;
+  for (int v : fl) nfail += v != 0;
+  return nfail;
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------------------------ C ABI
@@ -1512,6 +1655,7 @@ int scocg_green_columns(scocg_handle h, void* dst, int32_t dtype, int32_t dst_is
     const size_t esz = dtype == SCOCG_C128 ? 16 : 8;
     DevBuf tmp;
     void* d = dst;
+    if (dst_is_device) require_device_range(dst, (size_t)tot * esz, h->device, "dst");
     if (!dst_is_device) {
       tmp.alloc(tot * esz);
       d = tmp.p;
@@ -1548,6 +1692,57 @@ int scocg_apply_h(scocg_handle h, const void* x_dev, void* y_dev) {
       apply_h_impl<double, 8>(*h, x_dev, y_dev);
     else
       apply_h_impl<float, 16>(*h, x_dev, y_dev);
+    return SCOCG_OK;
+  });
+}
+
+int scocg_obm(scocg_handle h, int32_t K, int32_t M, int32_t L, const void* g_dev,
+              const void* sig_l_dev, const void* sig_r_dev, void* gt_dev, double* trans,
+              double* dos) {
+  return guarded([&]() -> int {
+    require(h != nullptr, "handle is NULL");
+    require(K >= 1 && K <= 16383, "K must be in 1..16383");
+    require(M >= 1 && L >= 0, "need M >= 1 and L >= 0");
+    const int64_t D = 2 * (int64_t)M + L;
+    require(D + 2 * (int64_t)M <= 65535 * 8, "2M + D too large for one grid row");
+    HIPCHK(hipSetDevice(h->device));
+    const size_t gbytes = sizeof(double2) * (size_t)K * D * D;
+    const size_t sbytes = sizeof(double2) * (size_t)K * M * M;
+    require_device_range(g_dev, gbytes, h->device, "g_dev");
+    require_device_range(sig_l_dev, sbytes, h->device, "sig_l_dev");
+    require_device_range(sig_r_dev, sbytes, h->device, "sig_r_dev");
+    DevBuf own;
+    double2* gt = static_cast<double2*>(gt_dev);
+    if (gt_dev) {
+      require_device_range(gt_dev, gbytes, h->device, "gt_dev");
+      auto apart = [&](const void* x, size_t xb, const char* what) {
+        const char* a = static_cast<const char*>(gt_dev);
+        const char* b = static_cast<const char*>(x);
+        require(a + gbytes <= b || b + xb <= a, std::string("gt_dev overlaps ") + what);
+      };
+      apart(g_dev, gbytes, "g_dev");
+      apart(sig_l_dev, sbytes, "sig_l_dev");
+      apart(sig_r_dev, sbytes, "sig_r_dev");
+    } else {
+      own.alloc(gbytes);
+      gt = own.as<double2>();
+    }
+    std::vector<double2> T;
+    std::vector<double> ds;
+    const int nfail = obm_run(*h, K, M, L, static_cast<const double2*>(g_dev),
+                              static_cast<const double2*>(sig_l_dev),
+                              static_cast<const double2*>(sig_r_dev), gt, T, ds);
+    if (trans)
+      for (int k = 0; k < K; ++k) {
+        trans[2 * k] = T[k].x;
+        trans[2 * k + 1] = T[k].y;
+      }
+    if (dos)
+      for (int k = 0; k < K; ++k) dos[k] = ds[k];
+    if (nfail) {
+      g_err = std::to_string(nfail) + " energies met a zero pivot (I - G Sigma singular)";
+      return SCOCG_BREAKDOWN;
+    }
     return SCOCG_OK;
   });
 }

@@ -23,7 +23,8 @@ PAIR_CONVERGED, PAIR_MAXITER, PAIR_BREAKDOWN, PAIR_STALLED = 0, 1, 2, 4
 C128, C64 = 0, 1
 
 EXPORTS = ("scocg_create", "scocg_solve", "scocg_batch_solve", "scocg_green_columns",
-           "scocg_apply_h", "scocg_destroy", "scocg_last_error", "scocg_struct_size")
+           "scocg_apply_h", "scocg_obm", "scocg_destroy", "scocg_last_error",
+           "scocg_struct_size")
 AUTO = -1  # SCOCG_AUTO: autotuned launch shape
 
 
@@ -94,6 +95,8 @@ def load(path: str = LIB_PATH):
     lib.scocg_struct_size.restype = C.c_int64
     lib.scocg_batch_solve.argtypes = [C.c_int32, P, P, C.POINTER(SolveOpts), P, P]
     lib.scocg_batch_solve.restype = C.c_int
+    lib.scocg_obm.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, P, P, P, P, P, P]
+    lib.scocg_obm.restype = C.c_int
     for which, mirror in enumerate((Grid, SolveOpts, Report, Problem)):
         if lib.scocg_struct_size(which) != C.sizeof(mirror):
             raise RuntimeError(f"{path}: {mirror.__name__} is {C.sizeof(mirror)} bytes here, "
@@ -200,6 +203,17 @@ class Handle:
         """scocg_apply_h on complex128 device vectors (torch tensors or raw pointers)."""
         _check(load().scocg_apply_h(self._h, _dev_ptr(x_dev), _dev_ptr(y_dev)))
 
+    def obm(self, K, M, L, g_dev, sig_l_dev, sig_r_dev, gt_dev=None):
+        """scocg_obm on device buffers (torch tensors or raw pointers), all complex128 and
+        column-major per energy.  Returns (rc, T [K] complex, dos [K])."""
+        trans = np.zeros(K, np.complex128)
+        dos = np.zeros(K, np.float64)
+        rc = load().scocg_obm(self._h, K, M, L, _dev_ptr(g_dev), _dev_ptr(sig_l_dev),
+                              _dev_ptr(sig_r_dev), None if gt_dev is None else _dev_ptr(gt_dev),
+                              trans.ctypes.data, dos.ctypes.data)
+        _check(rc)
+        return rc, trans, dos
+
     def destroy(self):
         if self._h:
             load().scocg_destroy(self._h)
@@ -269,3 +283,31 @@ def batch_solve(handles, problems, tol=1e-10, max_iter=100000, seed_switch=True,
     rc = lib.scocg_batch_solve(n, hs, probs, C.byref(o), reps, region_ms.ctypes.data)
     _check(rc)
     return rc, [_report_dict(reps[i], arrays[i]) for i in range(n)], region_ms
+
+
+def open_boundary(handle, z, idx, M, L, sig_l, sig_r, tol=1e-10, max_iter=100000, device=None,
+                  **solve_kw):
+    """Unperturbed columns on idx (scocg_solve), then the matching (scocg_obm).
+
+    idx = (left block, right block, extra rows) grid indices; sig_l, sig_r [K, M, M]
+    complex (matrix orientation).  Returns a dict with the solve's rc and report, the
+    matching's rc, T [K] complex, dos [K] and gt [K, D, D] (numpy, matrix orientation:
+    gt[k][r, c] = G_T(Z_k)[idx_r, idx_c])."""
+    import torch
+
+    dev = device if device is not None else torch.device("cuda", torch.cuda.current_device())
+    z = np.atleast_1d(np.asarray(z, np.complex128))
+    idx = np.asarray(idx, np.int64)
+    K, D = z.size, idx.size
+    assert D == 2 * M + L
+    rc, rep = handle.solve(z, idx, tol=tol, max_iter=max_iter, **solve_kw)
+    g = torch.empty((K, D, D), dtype=torch.complex128, device=dev)
+    handle.green_columns(out=g)
+    # column-major per energy: element (r, c) at r + M c, i.e. the transposed matrix
+    sl = torch.from_numpy(np.ascontiguousarray(np.transpose(sig_l, (0, 2, 1)))).to(dev)
+    sr = torch.from_numpy(np.ascontiguousarray(np.transpose(sig_r, (0, 2, 1)))).to(dev)
+    gt = torch.empty_like(g)
+    torch.cuda.synchronize(dev)
+    rc_obm, T, dos = handle.obm(K, M, L, g, sl, sr, gt)
+    return {"rc": rc, "report": rep, "rc_obm": rc_obm, "T": T, "dos": dos,
+            "gt": gt.cpu().numpy().transpose(0, 2, 1), "g": g.cpu().numpy().transpose(0, 2, 1)}

@@ -415,9 +415,12 @@ def obm_indices(nx, ny, nz, nf, extra=None):
 
 
 def interior_centres(nx, ny, nz, h, nf, n_atoms, rng, margin=1.5):
-    """Atom centres kept at least `margin` bohr away from the two boundary blocks."""
+    """Atom centres kept at least `margin` bohr away from the two boundary blocks
+    (all at the middle plane's height when the region is too short for that)."""
     zlo = nf * h + margin
     zhi = (nz - nf - 1) * h - margin
+    if zhi < zlo:
+        zlo = zhi = 0.5 * (nz - 1) * h
     return np.stack([rng.uniform(0, nx * h, n_atoms), rng.uniform(0, ny * h, n_atoms),
                      rng.uniform(zlo, zhi, n_atoms)], axis=1)
 

@@ -1,0 +1,180 @@
+"""GPU parity of the open-boundary matching entry point (scocg_obm) against the CPU
+oracle's direct inversion of Eq. 13, through the C ABI.
+
+The unperturbed columns come from the GPU solver (scocg_solve on the boundary
+blocks and extra rows); the lead self-energies are seeded inputs.  The oracle
+never sees a GPU value: it assembles Z - H_T - Sigma densely and inverts it.
+
+Tolerance.  The solver stops a column when its true residual is below tol, so
+each unperturbed column carries an error of at most tol * ||(Z - H)^{-1}|| <= tol/eta
+(H real symmetric, Im Z = eta).  The matching solves (I - G Sigma) X = G, so
+the perturbed block moves by at most ||(I - G Sigma)^{-1}|| (1 + ||Sigma|| ||G_T||)
+times that, plus rounding of the 2M x 2M elimination (~n eps cond).  The test
+takes ten times this first-order bound, computed from the oracle's own dense
+quantities.
+"""
+import time
+
+import numpy as np
+import pytest
+
+from oracle import obm as O
+from paper_1502_00081_amd import scocg, workload as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def log(msg):
+    print(f"[{time.strftime('%H:%M:%S')}] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    return torch.device("cuda", 0)
+
+
+def wire(nx, ny, nz, K, n_atoms=3, extra=True, seed=1502 + 17, elo=0.1, ehi=3.0, vzero=False):
+    p, M, L = W.obm_wire(nx=nx, ny=ny, nz=nz, K=K, n_atoms=n_atoms, seed=seed, elo=elo, ehi=ehi,
+                         extra_plane=extra, projectors=not vzero)
+    if vzero:
+        p = p.with_(vloc=np.zeros(p.n))
+    return p, M, L
+
+
+def gpu_obm(p, M, L, dev, tol=1e-11):
+    h = scocg.create_from_problem(p, precision=scocg.FP64)
+    try:
+        sl, sr = W.lead_self_energies(p.nx, p.ny, p.coef, p.z)
+        out = scocg.open_boundary(h, p.z, p.rhs_idx, M, L, sl, sr, tol=tol, device=dev)
+    finally:
+        h.destroy()
+    assert out["rc"] == scocg.OK, out["report"]["status"]
+    assert out["rc_obm"] == scocg.OK
+    return out, sl, sr
+
+
+def oracle_blocks(p, sl, sr, M):
+    """Perturbed G_T on idx (direct inversion), plus the quantities of the error bound."""
+    H = O.dense_h(p)
+    idx = p.rhs_idx
+    GT = O.perturbed_green(p, p.z, sl, sr, idx, H=H)
+    n = 2 * M
+    bound_factor = np.empty(p.z.size)
+    for k, zk in enumerate(p.z):
+        G0 = np.linalg.solve(zk * np.eye(p.n) - H, np.eye(p.n)[:, idx[:n]])[idx[:n]]
+        Sb = np.zeros((n, n), np.complex128)
+        Sb[:M, :M] = sl[k]
+        Sb[M:, M:] = sr[k]
+        Ainv = np.linalg.inv(np.eye(n) - G0 @ Sb)
+        bound_factor[k] = (np.linalg.norm(Ainv, 2)
+                           * (1 + np.linalg.norm(Sb, 2) * np.linalg.norm(GT[k], 2)))
+    return GT, bound_factor
+
+
+def check_against_oracle(p, M, L, out, sl, sr, tol):
+    GT, fac = oracle_blocks(p, sl, sr, M)
+    eta = p.z.imag.min()
+    n = 2 * M
+    worst = 0.0
+    for k in range(p.z.size):
+        bound = 10 * (tol / eta) * fac[k] + 1e-12 * np.abs(GT[k]).max()
+        d = np.abs(out["gt"][k] - GT[k]).max()
+        worst = max(worst, d / bound)
+        assert d <= bound, (k, d, bound)
+        T_ref = O.transmission(sl[k], sr[k], GT[k][M:n, :M])
+        # T is bilinear in G_T(right, left): its error is at most 2 ||Gamma||^2 ||Y|| dY
+        gl = np.linalg.norm(O.gamma(sl[k]), 2)
+        gr = np.linalg.norm(O.gamma(sr[k]), 2)
+        tb = 2 * gl * gr * np.linalg.norm(GT[k][M:n, :M], 2) * M * bound + 1e-12
+        assert abs(out["T"][k] - T_ref) <= tb, (k, out["T"][k], T_ref, tb)
+        assert abs(out["T"][k].imag) <= tb
+        if L:
+            dref = O.dos(GT[k][n:, n:])
+            assert abs(out["dos"][k] - dref) <= L * bound / np.pi + 1e-12, (k, out["dos"][k], dref)
+        else:
+            assert out["dos"][k] == 0.0
+    log(f"obm {p.name} K={p.z.size} M={M} L={L}: max |d|/bound {worst:.3e}, "
+        f"T = {np.round(out['T'].real, 4)}")
+
+
+@pytest.mark.parametrize("nx,ny,nz,K,extra", [(6, 6, 16, 6, True), (4, 5, 12, 5, False)])
+def test_obm_matches_direct_inversion(dev, nx, ny, nz, K, extra):
+    """Ragged tiles: M = 144 (two 64-row GEMM tiles and a tail), n = 288 (a 256-row
+    elimination tile and a tail), 36 extra rows; and a case without extra rows."""
+    p, M, L = wire(nx, ny, nz, K, extra=extra)
+    tol = 1e-11
+    out, sl, sr = gpu_obm(p, M, L, dev, tol)
+    check_against_oracle(p, M, L, out, sl, sr, tol)
+
+
+def test_obm_full_wire_workload(dev):
+    """The benchmarked configuration (8x8x32, M = 256, L = 64, 16 energies) end to end."""
+    p, M, L = W.obm_wire()
+    tol = 1e-11
+    out, sl, sr = gpu_obm(p, M, L, dev, tol)
+    check_against_oracle(p, M, L, out, sl, sr, tol)
+
+
+def test_ideal_wire_transmission_counts_open_channels(dev):
+    """V = 0, no projectors: the region is a piece of the leads; T is within O(eta L / v)
+    of the number of propagating modes, and equals the oracle's T at the same Z."""
+    from tests.test_obm_oracle import open_channels
+
+    p, M, L = wire(6, 6, 12, 4, n_atoms=0, extra=False, vzero=True, elo=0.4, ehi=2.8)
+    out, sl, sr = gpu_obm(p, M, L, dev, 1e-11)
+    n_ch = np.array([open_channels(p.coef, p.nx, p.ny, e) for e in p.z.real])
+    assert n_ch.min() >= 1
+    assert np.allclose(out["T"].real, n_ch, atol=0.05), (out["T"], n_ch)
+    check_against_oracle(p, M, L, out, sl, sr, 1e-11)
+
+
+def test_obm_argument_errors_and_breakdown(dev):
+    """Bad shapes, host pointers, short or overlapping buffers are rejected before any
+    launch; a NaN input ends in SCOCG_BREAKDOWN with NaN outputs; the handle stays usable."""
+    p, M, L = wire(4, 4, 10, 3, extra=False)
+    h = scocg.create_from_problem(p, precision=scocg.FP64)
+    lib = scocg.load()
+    try:
+        K, D = p.z.size, 2 * M
+        sl, sr = W.lead_self_energies(p.nx, p.ny, p.coef, p.z)
+        g = torch.zeros((K, D, D), dtype=torch.complex128, device=dev)
+        slt = torch.from_numpy(np.ascontiguousarray(sl.transpose(0, 2, 1))).to(dev)
+        srt = torch.from_numpy(np.ascontiguousarray(sr.transpose(0, 2, 1))).to(dev)
+        gt = torch.empty_like(g)
+        torch.cuda.synchronize()
+        T = np.zeros(2 * K)
+        ptr = scocg._dev_ptr
+        bad = [
+            (0, M, 0, ptr(g), ptr(slt), ptr(srt), ptr(gt)),          # K = 0
+            (K, 0, 0, ptr(g), ptr(slt), ptr(srt), ptr(gt)),          # M = 0
+            (K, M, -1, ptr(g), ptr(slt), ptr(srt), ptr(gt)),         # L < 0
+            (K, M, 0, None, ptr(slt), ptr(srt), ptr(gt)),            # NULL input
+            (K, M, 0, T.ctypes.data, ptr(slt), ptr(srt), ptr(gt)),   # host pointer
+            # buffers too small (far beyond the allocator's segment holding them)
+            (K, 10 * M, 0, ptr(g), ptr(slt), ptr(srt), ptr(gt)),
+            (K, M, 0, ptr(g), ptr(slt), ptr(srt), ptr(g)),           # output overlaps input
+        ]
+        for args in bad:
+            rc = lib.scocg_obm(h._h, *args, T.ctypes.data, None)
+            assert rc == scocg.EINVAL, (args, rc, scocg.last_error())
+        # g = 0 is a valid input: G_T = 0, T = 0
+        rc = lib.scocg_obm(h._h, K, M, 0, ptr(g), ptr(slt), ptr(srt), ptr(gt), T.ctypes.data,
+                           None)
+        assert rc == scocg.OK and np.all(T == 0) and torch.all(gt == 0)
+        g.fill_(float("nan"))
+        torch.cuda.synchronize()
+        rc = lib.scocg_obm(h._h, K, M, 0, ptr(g), ptr(slt), ptr(srt), ptr(gt), T.ctypes.data,
+                           None)
+        assert rc == scocg.BREAKDOWN and np.all(np.isnan(T)), (rc, T)
+        assert "pivot" in scocg.last_error()
+        # still usable: a real solve and matching afterwards
+        out = scocg.open_boundary(h, p.z, p.rhs_idx, M, 0, sl, sr, tol=1e-11, device=dev)
+        assert out["rc"] == scocg.OK and out["rc_obm"] == scocg.OK
+        assert np.all(np.isfinite(out["T"]))
+    finally:
+        h.destroy()
