@@ -263,11 +263,16 @@ def obm_run(a):
     srt = torch.from_numpy(np.ascontiguousarray(sr.transpose(0, 2, 1))).to(dev)
     say(f"obm wire: N={p.n}, K={K}, M={M}, L={L}, D={D}")
     tol = 1e-10
+    kw = dict(tol=tol, use_graph=True, tile=scocg.AUTO, zchunk=scocg.AUTO,
+              shift_chunk=scocg.AUTO)
+    rc, rep = h.solve(p.z, p.rhs_idx, **dict(kw, max_iter=16))  # autotune, cached in the handle
+    say(f"autotuned launch shape: tile {rep['tile']} zchunk {rep['zchunk']} shift chunk "
+        f"{rep['shift_chunk']}")
     solve_s, obm_s = [], []
     for i in range(a.warmup + a.steps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        rc, rep = h.solve(p.z, p.rhs_idx, tol=tol, use_graph=True)
+        rc, rep = h.solve(p.z, p.rhs_idx, **kw)
         h.green_columns(g)
         torch.cuda.synchronize()
         t1 = time.perf_counter()

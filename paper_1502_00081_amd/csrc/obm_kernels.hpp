@@ -10,8 +10,8 @@
 // and the extra rows follow as
 //     G_T(l, :) = G(l, :) + G(l, b) Sigma_b G_T(b, :).               (Eq. 18 on rows l)
 // Eqs. 19-24 are the two-by-two block elimination of the first system; here it
-// is solved as one n x n system by Gauss-Jordan elimination with partial
-// pivoting, one pivot per launch pair, all energies in one grid.
+// is solved as one n x n system by blocked Gauss-Jordan elimination with
+// partial pivoting, all energies in one grid.
 //
 // Every matrix is complex128 (double2: re, im), column-major: element (r, c)
 // of a matrix with leading dimension ld is at r + ld * c.
@@ -142,93 +142,183 @@ __global__ __launch_bounds__(256) void k_obm_init(const double2* __restrict__ g,
   }
 }
 
-// Pivot step j of Gauss-Jordan elimination on W_k (one workgroup per energy):
-// pick p = argmax_{i >= j} |W(i, j)| (the smallest such i on ties), swap rows p
-// and j over columns j.., scale row j by 1 / W(j, j), and store the multipliers
-// f(i) = W(i, j) for i != j (f(j) = 0).  A zero or non-finite pivot marks the
-// energy failed; its later steps are skipped.
-__global__ __launch_bounds__(256) void k_gj_pivot(double2* W, double2* f, int32_t* fail, int n,
-                                                  int ncol, int j) {
+// Blocked Gauss-Jordan elimination with partial pivoting on W_k = [A | RHS]
+// (n x ncol, leading dimension n), panels of GJ_W pivot columns.
+//
+// Panel kernel (one workgroup per energy) for pivots j = j0 .. j0+w-1: pick
+// p = argmax_{i >= j} |W(i, j)| (smallest i on ties), swap rows j and p over
+// every column from j on (so the columns right of the panel already hold
+// their final row order) and over the multipliers of the earlier pivots of
+// the panel, keep the pivot value and the multipliers f^(j)_i = W(i, j)
+// (i != j; f^(j)_j = 0), and eliminate inside the panel columns only.
+//
+// Update kernel (columns right of the panel): with v_J the rows j0.. of a
+// column and F the panel's multipliers, the panel's w eliminations amount to
+//   z_j = (v_j - sum_{j' < j} f^(j')_j z_j') / pivot_j          (forward sweep)
+//   new v_j = z_j - sum_{j' > j} f^(j')_j z_j'                   (rows j of the panel)
+//   new v_i = v_i - sum_j' f^(j')_i z_j'                         (every other row)
+// so each column is read and written once per panel instead of once per pivot.
+// A zero or non-finite pivot marks the energy failed; later kernels skip it.
+constexpr int GJ_W = 32;     // pivots per panel
+constexpr int GJ_CW = 16;    // columns per workgroup of the update
+constexpr int GJ_PNT = 512;  // threads of the panel kernel
+
+__global__ __launch_bounds__(GJ_PNT) void k_gj_panel(double2* W, double2* F, double2* pivv,
+                                                     int32_t* fail, int n, int ncol, int j0,
+                                                     int w) {
   const int k = blockIdx.x;
   if (fail[k]) return;
   double2* Wk = W + (size_t)k * n * ncol;
-  double2* fk = f + (size_t)k * n;
-  __shared__ double s_val[256];
-  __shared__ int s_idx[256];
+  double2* Fk = F + (size_t)k * n * GJ_W;
+  __shared__ double s_val[GJ_PNT];
+  __shared__ int s_idx[GJ_PNT];
   const int tid = threadIdx.x;
-  double best = -1.0;
-  int bi = n;
-  for (int i = j + tid; i < n; i += 256) {
-    const double a = cabs2(Wk[i + (size_t)n * j]);
-    if (a > best) {  // strict: keeps the smallest index within the thread
-      best = a;
-      bi = i;
+  const int jend = j0 + w;
+  for (int jj = 0; jj < w; ++jj) {
+    const int j = j0 + jj;
+    double best = -1.0;
+    int bi = n;
+    for (int i = j + tid; i < n; i += GJ_PNT) {
+      const double a = cabs2(Wk[i + (size_t)n * j]);
+      if (a > best) {
+        best = a;
+        bi = i;
+      }
     }
-  }
-  s_val[tid] = best;
-  s_idx[tid] = bi;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (tid < s) {
-      const double o = s_val[tid + s];
-      const int oi = s_idx[tid + s];
-      if (o > s_val[tid] || (o == s_val[tid] && oi < s_idx[tid])) {
-        s_val[tid] = o;
-        s_idx[tid] = oi;
+    s_val[tid] = best;
+    s_idx[tid] = bi;
+    __syncthreads();
+    for (int st = GJ_PNT / 2; st > 0; st >>= 1) {
+      if (tid < st) {
+        const double o = s_val[tid + st];
+        const int oi = s_idx[tid + st];
+        if (o > s_val[tid] || (o == s_val[tid] && oi < s_idx[tid])) {
+          s_val[tid] = o;
+          s_idx[tid] = oi;
+        }
+      }
+      __syncthreads();
+    }
+    const int p = s_idx[0];
+    const double pv = s_val[0];
+    __syncthreads();  // everyone has read the result before the arrays are reused
+    if (!(pv > 0.0) || !isfinite(pv) || p >= n) {
+      if (tid == 0) fail[k] = 1;
+      return;
+    }
+    if (p != j) {
+      for (int c = j + tid; c < ncol; c += GJ_PNT) {
+        double2* a = Wk + j + (size_t)n * c;
+        double2* b = Wk + p + (size_t)n * c;
+        const double2 t = *a;
+        *a = *b;
+        *b = t;
+      }
+      for (int c = tid; c < jj; c += GJ_PNT) {
+        double2* a = Fk + j + (size_t)n * c;
+        double2* b = Fk + p + (size_t)n * c;
+        const double2 t = *a;
+        *a = *b;
+        *b = t;
       }
     }
     __syncthreads();
-  }
-  const int p = s_idx[0];
-  const double pv = s_val[0];
-  if (!(pv > 0.0) || !isfinite(pv) || p >= n) {
-    if (tid == 0) fail[k] = 1;
-    return;
-  }
-  if (p != j) {
-    for (int c = j + tid; c < ncol; c += 256) {
+    const double2 piv = Wk[j + (size_t)n * j];
+    for (int i = tid; i < n; i += GJ_PNT)
+      Fk[i + (size_t)n * jj] = (i == j) ? double2{0.0, 0.0} : Wk[i + (size_t)n * j];
+    if (tid == 0) pivv[(size_t)k * GJ_W + jj] = piv;
+    __syncthreads();  // column j read before row j is rescaled
+    const double inv_den = 1.0 / cabs2(piv);
+    const double2 inv = {piv.x * inv_den, -piv.y * inv_den};
+    for (int c = j + 1 + tid; c < jend; c += GJ_PNT) {
       double2* a = Wk + j + (size_t)n * c;
-      double2* b = Wk + p + (size_t)n * c;
-      const double2 t = *a;
-      *a = *b;
-      *b = t;
+      *a = cmul(*a, inv);
     }
-  }
-  __syncthreads();
-  const double2 piv = Wk[j + (size_t)n * j];
-  const double inv_den = 1.0 / cabs2(piv);
-  const double2 inv = {piv.x * inv_den, -piv.y * inv_den};
-  for (int i = tid; i < n; i += 256) fk[i] = (i == j) ? double2{0.0, 0.0} : Wk[i + (size_t)n * j];
-  __syncthreads();  // column j read before row j is rescaled
-  for (int c = j + tid; c < ncol; c += 256) {
-    double2* a = Wk + j + (size_t)n * c;
-    *a = cmul(*a, inv);
+    __syncthreads();
+    // eliminate inside the panel: rows i != j, columns j+1 .. jend-1
+    const int pc = jend - j - 1;
+    for (int e = tid; e < n * pc; e += GJ_PNT) {
+      const int i = e % n, c = j + 1 + e / n;
+      if (i == j) continue;
+      const double2 fi = Fk[i + (size_t)n * jj];
+      const double2 pj = Wk[j + (size_t)n * c];
+      double2* a = Wk + i + (size_t)n * c;
+      double2 v = *a;
+      v.x = fma(-fi.x, pj.x, fma(fi.y, pj.y, v.x));
+      v.y = fma(-fi.x, pj.y, fma(-fi.y, pj.x, v.y));
+      *a = v;
+    }
+    __syncthreads();
   }
 }
 
-constexpr int GJ_COLS = 8;  // columns per thread in the elimination update
-
-// Elimination step j: W(i, c) -= f(i) W(j, c) for every row i != j (f(j) = 0)
-// and every column c > j.  grid = (row tiles of 256, column groups, energies).
-__global__ __launch_bounds__(256) void k_gj_elim(double2* W, const double2* __restrict__ f,
-                                                 const int32_t* __restrict__ fail, int n, int ncol,
-                                                 int j) {
-  const int k = blockIdx.z;
+// grid = (column groups of GJ_CW over columns j0+w .. ncol-1, energies), 256 threads.
+__global__ __launch_bounds__(256) void k_gj_update(double2* W, const double2* __restrict__ F,
+                                                   const double2* __restrict__ pivv,
+                                                   const int32_t* __restrict__ fail, int n,
+                                                   int ncol, int j0, int w) {
+  const int k = blockIdx.y;
   if (fail[k]) return;
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  const int cbeg = j + 1 + blockIdx.y * GJ_COLS;
-  if (i >= n || cbeg >= ncol) return;
+  const int c0 = j0 + w + blockIdx.x * GJ_CW;
+  if (c0 >= ncol) return;
+  const int nc = min(GJ_CW, ncol - c0);
   double2* Wk = W + (size_t)k * n * ncol;
-  const double2 fi = f[(size_t)k * n + i];
-  if (fi.x == 0.0 && fi.y == 0.0) return;
-  const int cend = min(cbeg + GJ_COLS, ncol);
-  for (int c = cbeg; c < cend; ++c) {
-    const double2 pj = Wk[j + (size_t)n * c];
-    double2* a = Wk + i + (size_t)n * c;
-    double2 v = *a;
-    v.x = fma(-fi.x, pj.x, fma(fi.y, pj.y, v.x));
-    v.y = fma(-fi.x, pj.y, fma(-fi.y, pj.x, v.y));
-    *a = v;
+  const double2* Fk = F + (size_t)k * n * GJ_W;
+  __shared__ double2 zs[GJ_W][GJ_CW];
+  __shared__ double2 fj[GJ_W][GJ_W + 1];  // fj[i][j'] = f^(j')_{j0+i}
+  __shared__ double2 pinv[GJ_W];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < w * GJ_CW; e += 256) {
+    const int i = e % w, c = e / w;
+    zs[i][c] = c < nc ? Wk[(j0 + i) + (size_t)n * (c0 + c)] : double2{0.0, 0.0};
+  }
+  for (int e = tid; e < w * w; e += 256) {
+    const int i = e % w, jp = e / w;
+    fj[i][jp] = Fk[(j0 + i) + (size_t)n * jp];
+  }
+  if (tid < w) {
+    const double2 pv = pivv[(size_t)k * GJ_W + tid];
+    const double d = 1.0 / cabs2(pv);
+    pinv[tid] = {pv.x * d, -pv.y * d};
+  }
+  __syncthreads();
+  // forward sweep over the panel's pivots
+  for (int jj = 0; jj < w; ++jj) {
+    if (tid < GJ_CW) zs[jj][tid] = cmul(zs[jj][tid], pinv[jj]);
+    __syncthreads();
+    const int rows = w - jj - 1;
+    for (int e = tid; e < rows * GJ_CW; e += 256) {
+      const int i = jj + 1 + e % rows, c = e / rows;
+      double2 v = zs[i][c];
+      const double2 f = fj[i][jj];
+      const double2 zz = zs[jj][c];
+      v.x = fma(-f.x, zz.x, fma(f.y, zz.y, v.x));
+      v.y = fma(-f.x, zz.y, fma(-f.y, zz.x, v.y));
+      zs[i][c] = v;
+    }
+    __syncthreads();
+  }
+  // every row: rows of the panel from z with the upper multipliers, others rank-w update
+  for (int i = tid; i < n; i += 256) {
+    const bool in_panel = i >= j0 && i < j0 + w;
+    double2 acc[GJ_CW];
+#pragma unroll
+    for (int c = 0; c < GJ_CW; ++c)
+      acc[c] = in_panel ? zs[i - j0][c]
+                        : (c < nc ? Wk[i + (size_t)n * (c0 + c)] : double2{0.0, 0.0});
+    const int jstart = in_panel ? i - j0 + 1 : 0;
+    for (int jp = jstart; jp < w; ++jp) {
+      const double2 f = Fk[i + (size_t)n * jp];
+#pragma unroll
+      for (int c = 0; c < GJ_CW; ++c) {
+        const double2 zz = zs[jp][c];
+        acc[c].x = fma(-f.x, zz.x, fma(f.y, zz.y, acc[c].x));
+        acc[c].y = fma(-f.x, zz.y, fma(-f.y, zz.x, acc[c].y));
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < GJ_CW; ++c)
+      if (c < nc) Wk[i + (size_t)n * (c0 + c)] = acc[c];
   }
 }
 

@@ -1331,9 +1331,10 @@ int obm_run(scocg_ctx& h, int K, int M, int L, const double2* g, const double2* 
             std::vector<double>& dos_host) {
   hipStream_t st = h.stream;
   const int n = 2 * M, D = 2 * M + L, ncol = n + D;
-  DevBuf W, f, fail, P, GR, U, Q, T, dos, lists;
+  DevBuf W, f, piv, fail, P, GR, U, Q, T, dos, lists;
   W.alloc(sizeof(double2) * (size_t)K * n * ncol);
-  f.alloc(sizeof(double2) * (size_t)K * n);
+  f.alloc(sizeof(double2) * (size_t)K * n * obm::GJ_W);
+  piv.alloc(sizeof(double2) * (size_t)K * obm::GJ_W);
   fail.alloc(sizeof(int32_t) * K);
   GR.alloc(sizeof(double2) * (size_t)K * M * M);
   U.alloc(sizeof(double2) * (size_t)K * M * M);
@@ -1396,17 +1397,17 @@ int obm_run(scocg_ctx& h, int K, int M, int L, const double2* g, const double2* 
                      n, D);
   KCHK();
   gemm(o_build, 4 * K, false, M, M, M, D, M, n, mone, one, 0);
-  // 2. Gauss-Jordan: W(:, n:) becomes G_T(b, :)
-  for (int j = 0; j < n; ++j) {
-    hipLaunchKernelGGL(obm::k_gj_pivot, dim3(K), dim3(256), 0, st, Wp, f.as<double2>(),
-                       fail.as<int32_t>(), n, ncol, j);
+  // 2. Gauss-Jordan by panels: W(:, n:) becomes G_T(b, :)
+  for (int j0 = 0; j0 < n; j0 += obm::GJ_W) {
+    const int w = std::min(obm::GJ_W, n - j0);
+    hipLaunchKernelGGL(obm::k_gj_panel, dim3(K), dim3(obm::GJ_PNT), 0, st, Wp, f.as<double2>(),
+                       piv.as<double2>(), fail.as<int32_t>(), n, ncol, j0, w);
     KCHK();
-    const int cols = ncol - j - 1;
-    if (cols > 0) {
-      hipLaunchKernelGGL(obm::k_gj_elim, dim3(nblocks(n, 256), nblocks(cols, obm::GJ_COLS), K),
-                         dim3(256), 0, st, Wp, f.as<double2>(), fail.as<int32_t>(), n, ncol, j);
-      KCHK();
-    }
+    const int cols = ncol - j0 - w;  // > 0: the RHS columns always follow
+    hipLaunchKernelGGL(obm::k_gj_update, dim3(nblocks(cols, obm::GJ_CW), K), dim3(256), 0, st,
+                       Wp, f.as<double2>(), piv.as<double2>(), fail.as<int32_t>(), n, ncol, j0,
+                       w);
+    KCHK();
   }
   // 3. output rows: boundary rows from X, extra rows G(l, :) + G(l, b) Sigma_b X
   hipLaunchKernelGGL(obm::k_obm_out, dim3(D, nblocks(D, 256), K), dim3(256), 0, st, Wp, g, gt, n,
