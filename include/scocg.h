@@ -125,6 +125,14 @@ typedef struct {
                             with (Sec. 3C): every (energy, column) pair runs its own
                             recurrence, nothing is shared between energies; outputs and
                             report as for the shifted solve */
+    int32_t aux_seed;    /* 1: start the seed recurrence at the energy seed_z, which need not
+                            be one of z (App., after Eq. A13: switching to an arbitrary
+                            point).  It is carried as one extra shift -- its pi follows
+                            Eq. A8 like every other shift, it is iterated to tol, and the
+                            switch of Eq. A13 leaves it once it has converged -- but its
+                            solution is neither returned nor reported.  init_seed is
+                            ignored.  Not with conventional = 1 or in scocg_batch_solve */
+    double seed_z[2];    /* (re, im) of that energy when aux_seed = 1; Im > 0 */
 } scocg_solve_opts;
 
 /* Autotuning: any of tile, zchunk, shift_chunk = SCOCG_AUTO makes scocg_solve time

@@ -151,6 +151,7 @@ struct scocg_ctx {
   struct Solve {
     bool ok = false;
     int B = 0, nb = 0, K = 0, R = 0, nS = 0, nwg = 0;
+    int Kout = 0;  // energies returned: K, or K - 1 when the last one is an auxiliary seed
     StencilGrid g{};
     int kch = 4;  // energies per workgroup of k_shift
     bool full = false;
@@ -856,9 +857,13 @@ struct Solver {
     }
     conv = o.conventional != 0;
     if (!conv) {
+      // an auxiliary seed energy is one more shift after the K returned ones
+      const int Kt = o.aux_seed ? K + 1 : K;
+      if (o.aux_seed) zh.push_back(mk(o.seed_z[0], o.seed_z[1]));
       upload(zk, zh, st);
-      alloc_state(K, R, full, nS, o);
-      seed0 = o.init_seed < 0 ? K / 2 : o.init_seed;
+      alloc_state(Kt, R, full, nS, o);
+      S.Kout = K;
+      seed0 = o.aux_seed ? K : (o.init_seed < 0 ? K / 2 : o.init_seed);
       return;
     }
     // conventional sweep: K*R single-energy systems, column k*R + j = (z_k, e_{rhs_j}); the
@@ -875,6 +880,7 @@ struct Solver {
     upload(S.rhs, rc, st);
     upload(zk, zcol, st);
     alloc_state(1, (int)RC, full, nS, o);
+    S.Kout = 1;
     seed0 = 0;
   }
 
@@ -945,7 +951,7 @@ struct Solver {
       seed_iters = std::max<int64_t>(seed_iters, ch[j].iters);
       nsw += ch[j].nswitch;
     }
-    for (int k = 0; k < K; ++k)
+    for (int k = 0; k < S.Kout; ++k)
       for (int j = 0; j < R; ++j) {
         const size_t so = ((size_t)(j / B) * K + k) * B + (j % B);
         const ShiftState& ss = shh[so];
@@ -1480,6 +1486,12 @@ scocg_solve_opts check_opts(const scocg_solve_opts* opts) {
               o.shift_chunk == 4 || o.shift_chunk == 16,
           "shift_chunk must be SCOCG_AUTO, 0, 1, 4 or 16");
   require(o.conventional == 0 || o.conventional == 1, "conventional must be 0 or 1");
+  require(o.aux_seed == 0 || o.aux_seed == 1, "aux_seed must be 0 or 1");
+  if (o.aux_seed) {
+    require(std::isfinite(o.seed_z[0]) && std::isfinite(o.seed_z[1]) && o.seed_z[1] > 0.0,
+            "seed_z must be finite with Im > 0");
+    require(o.conventional == 0, "aux_seed does not apply to the conventional sweep");
+  }
   return o;
 }
 
@@ -1630,6 +1642,7 @@ int scocg_batch_solve(int32_t n, const scocg_handle* hs, const scocg_problem* pr
     require(n >= 1 && hs != nullptr && probs != nullptr, "need n >= 1 handles and problems");
     const scocg_solve_opts o = check_opts(opts);
     require(o.init_seed == -1, "init_seed must be -1 (each region's middle energy) in a batch");
+    require(o.aux_seed == 0, "aux_seed is not offered in a batch");
     for (int i = 0; i < n; ++i) {
       const scocg_problem& p = probs[i];
       check_problem(hs[i], p.K, p.z, p.R, p.rhs_idx, p.nS, p.s_idx, o.full != 0);
@@ -1652,16 +1665,19 @@ int scocg_green_columns(scocg_handle h, void* dst, int32_t dtype, int32_t dst_is
     if (!h->last || !h->last->ok) throw Error(SCOCG_ENOSOLVE, "no successful solve to copy");
     HIPCHK(hipSetDevice(h->device));
     auto& S = *h->last;
-    const int64_t tot = (int64_t)S.K * S.R * S.nS;
+    // energy-major layout: the returned energies are the first Kout of the K gathered
+    const int64_t tot_all = (int64_t)S.K * S.R * S.nS;
+    const int64_t tot = (int64_t)S.Kout * S.R * S.nS;
     const size_t esz = dtype == SCOCG_C128 ? 16 : 8;
     DevBuf tmp;
     void* d = dst;
     if (dst_is_device) require_device_range(dst, (size_t)tot * esz, h->device, "dst");
-    if (!dst_is_device) {
-      tmp.alloc(tot * esz);
+    const bool staged = !dst_is_device || tot_all != tot;
+    if (staged) {
+      tmp.alloc(tot_all * esz);
       d = tmp.p;
     }
-    const unsigned nbk = nblocks(tot, WG);
+    const unsigned nbk = nblocks(tot_all, WG);
     if (S.B == 8) {
       if (dtype == SCOCG_C128)
         hipLaunchKernelGGL((k_gather_out<8, double2>), dim3(nbk), dim3(WG), 0, h->stream,
@@ -1678,8 +1694,10 @@ int scocg_green_columns(scocg_handle h, void* dst, int32_t dtype, int32_t dst_is
                            S.x.as<double2>(), static_cast<float2*>(d), S.K, S.R, S.nS);
     }
     KCHK();
-    if (!dst_is_device)
-      HIPCHK(hipMemcpyAsync(dst, d, tot * esz, hipMemcpyDeviceToHost, h->stream));
+    if (staged)
+      HIPCHK(hipMemcpyAsync(dst, d, tot * esz,
+                            dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                            h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     return SCOCG_OK;
   });

@@ -38,7 +38,8 @@ class SolveOpts(C.Structure):
                 ("seed_switch", C.c_int32), ("full", C.c_int32), ("refine", C.c_int32),
                 ("poll_every", C.c_int32), ("use_graph", C.c_int32), ("timing", C.c_int32),
                 ("tile", C.c_int32), ("zchunk", C.c_int32), ("shift_chunk", C.c_int32),
-                ("conventional", C.c_int32)]
+                ("conventional", C.c_int32), ("aux_seed", C.c_int32),
+                ("seed_z", C.c_double * 2)]
 
 
 class Report(C.Structure):
@@ -130,11 +131,15 @@ def _dev_ptr(t):
 
 
 def _opts(tol, max_iter, init_seed, seed_switch, full, refine, poll_every, use_graph, timing,
-          tile, zchunk, shift_chunk, conventional=False):
-    return SolveOpts(float(tol), int(max_iter), int(init_seed), int(bool(seed_switch)),
-                     int(bool(full)), int(refine), int(poll_every), int(bool(use_graph)),
-                     int(timing), int(tile), int(zchunk), int(shift_chunk),
-                     int(bool(conventional)))
+          tile, zchunk, shift_chunk, conventional=False, seed_z=None):
+    o = SolveOpts(float(tol), int(max_iter), int(init_seed), int(bool(seed_switch)),
+                  int(bool(full)), int(refine), int(poll_every), int(bool(use_graph)),
+                  int(timing), int(tile), int(zchunk), int(shift_chunk),
+                  int(bool(conventional)))
+    if seed_z is not None:
+        o.aux_seed = 1
+        o.seed_z[0], o.seed_z[1] = float(np.real(seed_z)), float(np.imag(seed_z))
+    return o
 
 
 def _new_report(K, R):
@@ -167,15 +172,16 @@ class Handle:
 
     def solve(self, z, rhs_idx, s_idx=None, tol=1e-10, max_iter=100000, init_seed=-1,
               seed_switch=True, full=False, refine=0, poll_every=0, use_graph=False, timing=0,
-              tile=0, zchunk=0, shift_chunk=0, conventional=False):
+              tile=0, zchunk=0, shift_chunk=0, conventional=False, seed_z=None):
         """scocg_solve; returns (rc, report dict with [K, R] arrays).  conventional=True runs
-        every (energy, column) pair as its own recurrence (the comparison sweep)."""
+        every (energy, column) pair as its own recurrence (the comparison sweep).  seed_z (a
+        complex energy, not necessarily one of z) starts the seed recurrence there."""
         lib = load()
         z = _c(z, np.complex128)
         rhs = _c(rhs_idx, np.int64)
         sp = None if s_idx is None else _c(s_idx, np.int64)
         o = _opts(tol, max_iter, init_seed, seed_switch, full, refine, poll_every, use_graph,
-                  timing, tile, zchunk, shift_chunk, conventional)
+                  timing, tile, zchunk, shift_chunk, conventional, seed_z)
         rep, arrays = _new_report(z.size, rhs.size)
         rc = lib.scocg_solve(self._h, z.size, z.ctypes.data, rhs.size, rhs.ctypes.data,
                              0 if sp is None else sp.size,

@@ -632,3 +632,38 @@ def test_conventional_mixed_refined_and_autotuned_mixed(dev):
     assert rc == scocg.OK and ra["tuned"]
     d2 = np.linalg.norm(Ga - G64, axis=2)
     assert (d2 <= (ra["true_resid"] + rep64["true_resid"]) / eta).all()
+
+
+def test_seed_at_an_energy_outside_the_sampled_set(dev):
+    """aux_seed: the recurrence starts at an energy that is not returned (Appendix, after
+    Eq. A13); every column switches to a sampled energy once that seed converges, every
+    returned pair reaches the oracle's column, and only the K sampled energies come back
+    (host and device copies).  Misuse is rejected."""
+    p = small(8, 8, 12, 4, True, K=6)
+    h = scocg.create_from_problem(p, precision=scocg.FP64)
+    try:
+        rc, rep = h.solve(p.z, p.rhs_idx, tol=1e-11, full=True, seed_z=0.05 + 0.3j)
+        assert rc == scocg.OK, rep["status"]
+        assert rep["n_switches"] >= p.rhs_idx.size
+        G = h.green_columns()
+        assert G.shape == (p.z.size, p.rhs_idx.size, p.n)
+        Gd = torch.empty((p.z.size, p.rhs_idx.size, p.n), dtype=torch.complex128, device=dev)
+        h.green_columns(out=Gd)
+        assert np.array_equal(Gd.cpu().numpy(), G)
+        ref, _ = oracle_columns(p, tol=1e-13)
+        assert (true_residuals(p, G) <= 1.1e-11).all()
+        rel = np.linalg.norm(G - ref, axis=2) / np.linalg.norm(ref, axis=2)
+        assert rel.max() <= 1e-8
+        say(f"aux seed: {rep['seed_iters']} iterations, {rep['n_switches']} switches, "
+            f"max rel {rel.max():.2e}")
+        with pytest.raises(scocg.ScocgError):
+            h.solve(p.z, p.rhs_idx, tol=1e-11, seed_z=0.1 - 0.01j)
+        with pytest.raises(scocg.ScocgError):
+            h.solve(p.z, p.rhs_idx, tol=1e-11, seed_z=0.1 + 0.01j, conventional=True)
+        # still usable, and a seed equal to a sampled energy changes nothing beyond rounding
+        rc, rep2 = h.solve(p.z, p.rhs_idx, tol=1e-11, full=True, seed_z=p.z[2])
+        assert rc == scocg.OK
+        G2 = h.green_columns()
+        assert np.linalg.norm(G2 - ref, axis=2).max() <= 1e-8 * np.linalg.norm(ref, axis=2).min()
+    finally:
+        h.destroy()

@@ -230,6 +230,23 @@ def test_seed_switching_and_initial_seed_do_not_change_results():
                 assert np.linalg.norm(r["x"][k] - ref) <= 1e-7 * np.linalg.norm(ref)
 
 
+def test_seed_at_an_energy_outside_the_sampled_set():
+    """A seed at an arbitrary energy (here with a larger imaginary part, so it converges
+    first), carried as one more shift: after the switch of Eq. A13 to a sampled energy,
+    every sampled shift still reaches its dense solution (Appendix, after Eq. A13)."""
+    p = small_problem(8, 8, 12, projectors=True, eta=1e-3, K=6)
+    H = D.dense_h(p)
+    b = unit(p.n, p.rhs_idx[0])
+    z_aux = 0.05 + 0.3j
+    z = np.concatenate([p.z, [z_aux]])
+    r = oracle.shifted_cocg(p, z, b, seed0=p.z.size, seed_switch=True, tol=1e-11)
+    assert r["n_switch"] >= 1 and r["seed_final"] != p.z.size
+    assert (r["status"] == oracle.CONVERGED).all()
+    for k in range(z.size):
+        ref = np.linalg.solve(z[k] * np.eye(p.n) - H, b)
+        assert np.linalg.norm(r["x"][k] - ref) <= 1e-8 * np.linalg.norm(ref)
+
+
 def test_early_seed_switch_keeps_every_shift_exact():
     """Seed below the spectrum converges long before the others; after the
     switch (Eq. A13) every shift still reaches its dense solution."""
