@@ -245,6 +245,24 @@ def sweep_run(a):
                       "unit": "ms", "data": "synthetic", "sweep": out}), flush=True)
 
 
+def obm_cpu_baseline(p, M, sl, sr, n_energies=2):
+    """The oracle's direct inversion of Eq. 13 plus Eq. 14 on the first energies of the
+    workload (dense H_T assembled once, outside the timing), as energies/s."""
+    from threadpoolctl import threadpool_info
+    from oracle import obm as O
+    H = O.dense_h(p)
+    z = p.z[:n_energies]
+    t0 = time.perf_counter()
+    G = O.perturbed_green(p, z, sl[:n_energies], sr[:n_energies], p.rhs_idx, H=H)
+    for k in range(z.size):
+        O.transmission(sl[k], sr[k], G[k][M:2 * M, :M])
+    dt = time.perf_counter() - t0
+    threads = max([t.get("num_threads", 1) for t in threadpool_info()] or [1])
+    return {"value": z.size / dt, "unit": "energies/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{z.size} of the {p.z.size} energies, dense solve of the N = {p.n} "
+                      f"Eq. 13 matrix with {p.rhs_idx.size} right-hand sides each"}
+
+
 def obm_run(a):
     """Open-boundary matching on the 8x8x32 scatterer wire (M = 256 rows per boundary
     block, 64 extra rows of the middle plane, 16 energies in [0.1, 3.0] Ha): the
@@ -268,7 +286,7 @@ def obm_run(a):
     rc, rep = h.solve(p.z, p.rhs_idx, **dict(kw, max_iter=16))  # autotune, cached in the handle
     say(f"autotuned launch shape: tile {rep['tile']} zchunk {rep['zchunk']} shift chunk "
         f"{rep['shift_chunk']}")
-    solve_s, obm_s = [], []
+    solve_s, obm_s, phases = [], [], []
     for i in range(a.warmup + a.steps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -276,20 +294,30 @@ def obm_run(a):
         h.green_columns(g)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        rc2, T, dos = h.obm(K, M, L, g, slt, srt, gt)
+        ph = np.zeros(4)
+        rc2, T, dos = h.obm(K, M, L, g, slt, srt, gt, phase_ms=ph)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         assert rc == scocg.OK and rc2 == scocg.OK, (rc, rc2)
         if i >= a.warmup:
             solve_s.append(t1 - t0)
             obm_s.append(t2 - t1)
+            phases.append(ph)
         say(f"{'warmup' if i < a.warmup else 'step'} {i}: solve {1e3 * (t1 - t0):.1f} ms "
             f"({rep['seed_iters']} iterations), matching {1e3 * (t2 - t1):.1f} ms")
     h.destroy()
     ts, to = float(np.mean(solve_s)), float(np.mean(obm_s))
+    ph = np.mean(phases, axis=0)
     ncol = n + D
-    # Gauss-Jordan elimination: step j reads and writes rows != j of columns j+1..ncol-1
-    elim_bytes = K * sum(32 * n * (ncol - j - 1) for j in range(n))
+    # panel updates (dominant arithmetic of the matching): for every panel of w pivots,
+    # each column right of it gets a rank-w update of all n rows (8 w flops per element,
+    # one complex FMA per pivot) and is read and written once (32 bytes per element)
+    panels = [(j0, min(32, n - j0)) for j0 in range(0, n, 32)]
+    upd_flops = K * sum(8 * w * n * (ncol - j0 - w) for j0, w in panels)
+    upd_bytes = K * sum(32 * n * (ncol - j0 - w) for j0, w in panels)
+    cpu = None
+    if not a.no_cpu_baseline:
+        cpu = obm_cpu_baseline(p, M, sl, sr)
     print(json.dumps({
         "metric": "transmission + DOS energies/s (unperturbed solve + open-boundary matching)",
         "value": K / (ts + to), "unit": "energies/s", "n_gpus": 1, "steps": a.steps,
@@ -298,7 +326,13 @@ def obm_run(a):
         "config": {"workload": p.name, "energies": K, "block_rows": M, "extra_rows": L,
                    "tol": tol},
         "solve_ms": ts * 1e3, "matching_ms": to * 1e3,
-        "matching_elimination_bytes": elim_bytes,
+        "matching_phase_ms": {"setup_products": ph[0], "panels": ph[1], "panel_updates": ph[2],
+                              "outputs_T_dos": ph[3]},
+        "roofline": {"kernel": "k_gj_update", "bound": "alu",
+                     "achieved": upd_flops / (ph[2] * 1e-3) / 1e12, "peak": 78.6,
+                     "unit": "TFLOP/s", "frac": upd_flops / (ph[2] * 1e-3) / 1e12 / 78.6,
+                     "traffic": None, "bytes_per_s": upd_bytes / (ph[2] * 1e-3) / 1e9},
+        "cpu_baseline": cpu,
         "T": [round(float(x), 6) for x in T.real], "dos": [round(float(x), 6) for x in dos]}),
         flush=True)
 

@@ -270,6 +270,9 @@ int scocg_apply_h(scocg_handle h, const void *x_dev, void *y_dev);
  *              may not overlap an input.
  *   trans      [K][2] host output (re, im of T; im vanishes up to rounding) or NULL.
  *   dos        [K] host output or NULL (0 when L = 0).
+ *   phase_ms   [4] host output or NULL: device time of the phases, from HIP events
+ *              around each launch -- 0 forming I - G_bb Sigma_b, 1 elimination panels,
+ *              2 panel updates of the other columns, 3 output rows, T and DOS.
  * Work runs on the handle's stream; the call returns after it completes.  The
  * handle's operator and last solve are not used or changed.  Device workspace of
  * about 16 K (2M (2M + D) + 3 M^2 + 2 L M) bytes is allocated for the call.
@@ -278,7 +281,7 @@ int scocg_apply_h(scocg_handle h, const void *x_dev, void *y_dev);
  */
 int scocg_obm(scocg_handle h, int32_t K, int32_t M, int32_t L, const void *g_dev,
               const void *sig_l_dev, const void *sig_r_dev, void *gt_dev, double *trans,
-              double *dos);
+              double *dos, double *phase_ms);
 
 /* Release every device buffer of the handle.  NULL is ignored. */
 void scocg_destroy(scocg_handle h);

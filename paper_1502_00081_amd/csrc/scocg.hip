@@ -1334,8 +1334,18 @@ void require_device_range(const void* p, size_t bytes, int device, const char* n
 // Returns the number of energies whose elimination met a zero pivot.
 int obm_run(scocg_ctx& h, int K, int M, int L, const double2* g, const double2* sig_l,
             const double2* sig_r, double2* gt, std::vector<double2>& T_host,
-            std::vector<double>& dos_host) {
+            std::vector<double>& dos_host, double* phase_ms) {
   hipStream_t st = h.stream;
+  // optional device timing: an event pair around every launch of each phase
+  // (0 setup products, 1 panels, 2 panel updates, 3 outputs, T and DOS)
+  std::vector<std::unique_ptr<Event>> evs;
+  std::vector<int> ev_phase;
+  auto mark = [&](int phase) {
+    if (!phase_ms) return;
+    evs.emplace_back(new Event());
+    HIPCHK(hipEventRecord(evs.back()->e, st));
+    ev_phase.push_back(phase);
+  };
   const int n = 2 * M, D = 2 * M + L, ncol = n + D;
   DevBuf W, f, piv, fail, P, GR, U, Q, T, dos, lists;
   W.alloc(sizeof(double2) * (size_t)K * n * ncol);
@@ -1399,23 +1409,30 @@ int obm_run(scocg_ctx& h, int K, int M, int L, const double2* g, const double2* 
 
   // 1. W = [I | G(b, :)], then W(:, 0:n) -= G_bb Sigma_b
   HIPCHK(hipMemsetAsync(fail.p, 0, fail.bytes, st));
+  mark(0);
   hipLaunchKernelGGL(obm::k_obm_init, dim3(ncol, nblocks(n, 256), K), dim3(256), 0, st, g, Wp,
                      n, D);
   KCHK();
   gemm(o_build, 4 * K, false, M, M, M, D, M, n, mone, one, 0);
+  mark(0);
   // 2. Gauss-Jordan by panels: W(:, n:) becomes G_T(b, :)
   for (int j0 = 0; j0 < n; j0 += obm::GJ_W) {
     const int w = std::min(obm::GJ_W, n - j0);
+    mark(1);
     hipLaunchKernelGGL(obm::k_gj_panel, dim3(K), dim3(obm::GJ_PNT), 0, st, Wp, f.as<double2>(),
                        piv.as<double2>(), fail.as<int32_t>(), n, ncol, j0, w);
     KCHK();
     const int cols = ncol - j0 - w;  // > 0: the RHS columns always follow
+    mark(1);
+    mark(2);
     hipLaunchKernelGGL(obm::k_gj_update, dim3(nblocks(cols, obm::GJ_CW), K), dim3(256), 0, st,
                        Wp, f.as<double2>(), piv.as<double2>(), fail.as<int32_t>(), n, ncol, j0,
                        w);
     KCHK();
+    mark(2);
   }
   // 3. output rows: boundary rows from X, extra rows G(l, :) + G(l, b) Sigma_b X
+  mark(3);
   hipLaunchKernelGGL(obm::k_obm_out, dim3(D, nblocks(D, 256), K), dim3(256), 0, st, Wp, g, gt, n,
                      D);
   KCHK();
@@ -1435,6 +1452,7 @@ int obm_run(scocg_ctx& h, int K, int M, int L, const double2* g, const double2* 
   hipLaunchKernelGGL(obm::k_dos, dim3(K), dim3(256), 0, st, gt, dos.as<double>(),
                      fail.as<int32_t>(), n, D, L);
   KCHK();
+  mark(3);
   std::vector<int32_t> fl(K);
   T_host.resize(K);
   dos_host.resize(K);
@@ -1442,6 +1460,11 @@ int obm_run(scocg_ctx& h, int K, int M, int L, const double2* g, const double2* 
   HIPCHK(hipMemcpyAsync(dos_host.data(), dos.p, dos.bytes, hipMemcpyDeviceToHost, st));
   HIPCHK(hipMemcpyAsync(fl.data(), fail.p, fail.bytes, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));  // every workspace buffer is freed on return
+  if (phase_ms) {
+    for (int q = 0; q < 4; ++q) phase_ms[q] = 0.0;
+    for (size_t e = 0; e + 1 < evs.size(); e += 2)
+      phase_ms[ev_phase[e]] += elapsed_ms(*evs[e], *evs[e + 1]);
+  }
   int nfail = 0;
   for (int v : fl) nfail += v != 0;
   return nfail;
@@ -1717,7 +1740,7 @@ int scocg_apply_h(scocg_handle h, const void* x_dev, void* y_dev) {
 
 int scocg_obm(scocg_handle h, int32_t K, int32_t M, int32_t L, const void* g_dev,
               const void* sig_l_dev, const void* sig_r_dev, void* gt_dev, double* trans,
-              double* dos) {
+              double* dos, double* phase_ms) {
   return guarded([&]() -> int {
     require(h != nullptr, "handle is NULL");
     require(K >= 1 && K <= 16383, "K must be in 1..16383");
@@ -1750,7 +1773,7 @@ int scocg_obm(scocg_handle h, int32_t K, int32_t M, int32_t L, const void* g_dev
     std::vector<double> ds;
     const int nfail = obm_run(*h, K, M, L, static_cast<const double2*>(g_dev),
                               static_cast<const double2*>(sig_l_dev),
-                              static_cast<const double2*>(sig_r_dev), gt, T, ds);
+                              static_cast<const double2*>(sig_r_dev), gt, T, ds, phase_ms);
     if (trans)
       for (int k = 0; k < K; ++k) {
         trans[2 * k] = T[k].x;

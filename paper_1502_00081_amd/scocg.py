@@ -96,7 +96,7 @@ def load(path: str = LIB_PATH):
     lib.scocg_struct_size.restype = C.c_int64
     lib.scocg_batch_solve.argtypes = [C.c_int32, P, P, C.POINTER(SolveOpts), P, P]
     lib.scocg_batch_solve.restype = C.c_int
-    lib.scocg_obm.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, P, P, P, P, P, P]
+    lib.scocg_obm.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, P, P, P, P, P, P, P]
     lib.scocg_obm.restype = C.c_int
     for which, mirror in enumerate((Grid, SolveOpts, Report, Problem)):
         if lib.scocg_struct_size(which) != C.sizeof(mirror):
@@ -209,14 +209,18 @@ class Handle:
         """scocg_apply_h on complex128 device vectors (torch tensors or raw pointers)."""
         _check(load().scocg_apply_h(self._h, _dev_ptr(x_dev), _dev_ptr(y_dev)))
 
-    def obm(self, K, M, L, g_dev, sig_l_dev, sig_r_dev, gt_dev=None):
+    def obm(self, K, M, L, g_dev, sig_l_dev, sig_r_dev, gt_dev=None, phase_ms=None):
         """scocg_obm on device buffers (torch tensors or raw pointers), all complex128 and
-        column-major per energy.  Returns (rc, T [K] complex, dos [K])."""
+        column-major per energy.  Returns (rc, T [K] complex, dos [K]); phase_ms (a float64
+        array of 4) receives the device time per phase when given."""
         trans = np.zeros(K, np.complex128)
         dos = np.zeros(K, np.float64)
+        if phase_ms is not None:
+            assert phase_ms.dtype == np.float64 and phase_ms.size >= 4
         rc = load().scocg_obm(self._h, K, M, L, _dev_ptr(g_dev), _dev_ptr(sig_l_dev),
                               _dev_ptr(sig_r_dev), None if gt_dev is None else _dev_ptr(gt_dev),
-                              trans.ctypes.data, dos.ctypes.data)
+                              trans.ctypes.data, dos.ctypes.data,
+                              None if phase_ms is None else phase_ms.ctypes.data)
         _check(rc)
         return rc, trans, dos
 

@@ -160,16 +160,18 @@ def test_obm_argument_errors_and_breakdown(dev):
             (K, M, 0, ptr(g), ptr(slt), ptr(srt), ptr(g)),           # output overlaps input
         ]
         for args in bad:
-            rc = lib.scocg_obm(h._h, *args, T.ctypes.data, None)
+            rc = lib.scocg_obm(h._h, *args, T.ctypes.data, None, None)
             assert rc == scocg.EINVAL, (args, rc, scocg.last_error())
         # g = 0 is a valid input: G_T = 0, T = 0
+        ph = np.full(4, -1.0)
         rc = lib.scocg_obm(h._h, K, M, 0, ptr(g), ptr(slt), ptr(srt), ptr(gt), T.ctypes.data,
-                           None)
+                           None, ph.ctypes.data)
         assert rc == scocg.OK and np.all(T == 0) and torch.all(gt == 0)
+        assert np.all(ph > 0), ph
         g.fill_(float("nan"))
         torch.cuda.synchronize()
         rc = lib.scocg_obm(h._h, K, M, 0, ptr(g), ptr(slt), ptr(srt), ptr(gt), T.ctypes.data,
-                           None)
+                           None, None)
         assert rc == scocg.BREAKDOWN and np.all(np.isnan(T)), (rc, T)
         assert "pivot" in scocg.last_error()
         # still usable: a real solve and matching afterwards
