@@ -57,6 +57,8 @@ def parse():
                     help="explicit launch shape 'tile,zchunk,shift_chunk' (no autotuning)")
     ap.add_argument("--no-sequential", action="store_true",
                     help="batched_regions: skip the region-by-region comparison")
+    ap.add_argument("--no-symmetric", action="store_true",
+                    help="obm_wire: keep every row of every column block (no mirroring)")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed-vs-FP64 comparison on the 16x16x24 all-plane workload")
     return ap.parse_args()
@@ -282,7 +284,7 @@ def obm_run(a):
     say(f"obm wire: N={p.n}, K={K}, M={M}, L={L}, D={D}")
     tol = 1e-10
     kw = dict(tol=tol, use_graph=True, tile=scocg.AUTO, zchunk=scocg.AUTO,
-              shift_chunk=scocg.AUTO)
+              shift_chunk=scocg.AUTO, symmetric=not a.no_symmetric)
     rc, rep = h.solve(p.z, p.rhs_idx, **dict(kw, max_iter=16))  # autotune, cached in the handle
     say(f"autotuned launch shape: tile {rep['tile']} zchunk {rep['zchunk']} shift chunk "
         f"{rep['shift_chunk']}")
@@ -324,7 +326,7 @@ def obm_run(a):
         "warmup": a.warmup, "ms_per_step": (ts + to) * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": p.name, "energies": K, "block_rows": M, "extra_rows": L,
-                   "tol": tol},
+                   "tol": tol, "symmetric_rows": not a.no_symmetric},
         "solve_ms": ts * 1e3, "matching_ms": to * 1e3,
         "matching_phase_ms": {"setup_products": ph[0], "panels": ph[1], "panel_updates": ph[2],
                               "outputs_T_dos": ph[3]},

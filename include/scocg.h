@@ -133,6 +133,12 @@ typedef struct {
                             solution is neither returned nor reported.  init_seed is
                             ignored.  Not with conventional = 1 or in scocg_batch_solve */
     double seed_z[2];    /* (re, im) of that energy when aux_seed = 1; Im > 0 */
+    int32_t symmetric;   /* 1: use G(S_i, e_j) = G(S_j, e_i) (Z - H is complex symmetric):
+                            the column block of columns j0.. updates x^{(k)}, p^{(k)} only on
+                            rows i >= j0 and the copy-out fills the other rows from the
+                            mirror column -- about half the shift-vector work.  Needs
+                            S = the RHS set (s_idx NULL), full = 0, conventional = 0.  The
+                            mirrored entries carry the mirror column's error (same tol) */
 } scocg_solve_opts;
 
 /* Autotuning: any of tile, zchunk, shift_chunk = SCOCG_AUTO makes scocg_solve time

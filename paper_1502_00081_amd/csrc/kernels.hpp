@@ -158,6 +158,7 @@ struct ShiftArgs {
   gptr<cT> p;                      // [nb][K][nS][B]
   int gx, gy;                 // workgroups per block along rows and along the list
   int kch;                    // list entries (energies) per workgroup
+  int sym;                    // 1: S is the RHS set and block cb keeps rows i >= cb*B only
 };
 
 template <typename T>
@@ -1135,6 +1136,9 @@ __device__ __forceinline__ void shift_body(const ShiftArgs<T>& a, int lb, int pa
   const int64_t gid = (int64_t)bx * NTH + threadIdx.x;
   if (gid >= (int64_t)nS * B) return;
   const int i = (int)(gid / B), c = (int)(gid % B);
+  // complex symmetry: rows below the block's first column are the mirror of columns
+  // already kept by an earlier block, G(S_i, e_j) = G(S_j, e_i)
+  if (a.sym && i < cb * B) return;
   const int64_t row = a.srow ? (int64_t)a.srow[i] : (int64_t)i;
   const cT* rnew = par ? a.rnew[0] : a.rnew[1];  // r_{n+1}: buffer par ^ 1
   const double2 rv = to_d(rnew[(int64_t)cb * a.bstride + row * B + c]);
@@ -1473,16 +1477,22 @@ __global__ void k_add_correction(double2* __restrict__ xout, const double2* __re
   xo = mk(xo.x + back[j] * dv.x, xo.y + back[j] * dv.y);
 }
 
-// G[k][j][i] = x[cb][k][i][c]  (j = cb*B + c), complex128 or complex64
+// G[k][j][i] = x[cb][k][i][c]  (j = cb*B + c), complex128 or complex64.  sym: rows
+// i < cb*B were not kept for block cb; they are row j of column i (S = RHS set).
 template <int B, typename O>
 __global__ void k_gather_out(const double2* __restrict__ x, O* __restrict__ out, int K, int R,
-                             int nS) {
+                             int nS, int sym) {
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t tot = (int64_t)K * R * nS;
   if (gid >= tot) return;
-  const int i = (int)(gid % nS);
-  const int j = (int)((gid / nS) % R);
+  int i = (int)(gid % nS);
+  int j = (int)((gid / nS) % R);
   const int k = (int)(gid / ((int64_t)nS * R));
+  if (sym && i < (j / B) * B) {
+    const int t = i;
+    i = j;
+    j = t;
+  }
   const int cb = j / B, c = j % B;
   const double2 v = x[(((int64_t)cb * K + k) * nS + i) * B + c];
   O o;

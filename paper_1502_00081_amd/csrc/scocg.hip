@@ -152,6 +152,7 @@ struct scocg_ctx {
     bool ok = false;
     int B = 0, nb = 0, K = 0, R = 0, nS = 0, nwg = 0;
     int Kout = 0;  // energies returned: K, or K - 1 when the last one is an auxiliary seed
+    int sym = 0;   // rows below each block's first column are taken from the mirror column
     StencilGrid g{};
     int kch = 4;  // energies per workgroup of k_shift
     bool full = false;
@@ -354,6 +355,7 @@ struct Solver {
     sa.gx = (int)nblocks((int64_t)S.nS * B, nth);
     sa.gy = (int)nblocks(S.K, kch);
     sa.kch = kch;
+    sa.sym = S.sym;
     return sa;
   }
 
@@ -856,6 +858,7 @@ struct Solver {
       upload(S.srow, sr, st);
     }
     conv = o.conventional != 0;
+    S.sym = o.symmetric;
     if (!conv) {
       // an auxiliary seed energy is one more shift after the K returned ones
       const int Kt = o.aux_seed ? K + 1 : K;
@@ -1510,6 +1513,9 @@ scocg_solve_opts check_opts(const scocg_solve_opts* opts) {
           "shift_chunk must be SCOCG_AUTO, 0, 1, 4 or 16");
   require(o.conventional == 0 || o.conventional == 1, "conventional must be 0 or 1");
   require(o.aux_seed == 0 || o.aux_seed == 1, "aux_seed must be 0 or 1");
+  require(o.symmetric == 0 || o.symmetric == 1, "symmetric must be 0 or 1");
+  require(!o.symmetric || (o.full == 0 && o.conventional == 0),
+          "symmetric needs projected storage and the shifted solve");
   if (o.aux_seed) {
     require(std::isfinite(o.seed_z[0]) && std::isfinite(o.seed_z[1]) && o.seed_z[1] > 0.0,
             "seed_z must be finite with Im > 0");
@@ -1647,6 +1653,7 @@ int scocg_solve(scocg_handle h, int32_t K, const double* z, int32_t R, const int
   return guarded([&]() -> int {
     const scocg_solve_opts o = check_opts(opts);
     check_problem(h, K, z, R, rhs_idx, nS, s_idx, o.full != 0);
+    require(!o.symmetric || s_idx == nullptr, "symmetric needs S = the RHS set (s_idx NULL)");
     require(o.init_seed >= -1 && o.init_seed < K, "init_seed out of range");
     HIPCHK(hipSetDevice(h->device));
     h->last.reset(new scocg_ctx::Solve());
@@ -1669,6 +1676,7 @@ int scocg_batch_solve(int32_t n, const scocg_handle* hs, const scocg_problem* pr
     for (int i = 0; i < n; ++i) {
       const scocg_problem& p = probs[i];
       check_problem(hs[i], p.K, p.z, p.R, p.rhs_idx, p.nS, p.s_idx, o.full != 0);
+      require(!o.symmetric || p.s_idx == nullptr, "symmetric needs S = the RHS set (s_idx NULL)");
       require(hs[i]->device == hs[0]->device && hs[i]->stream == hs[0]->stream,
               "batched handles need one device and one stream");
       require(hs[i]->precision == hs[0]->precision && hs[i]->nf == hs[0]->nf,
@@ -1704,17 +1712,17 @@ int scocg_green_columns(scocg_handle h, void* dst, int32_t dtype, int32_t dst_is
     if (S.B == 8) {
       if (dtype == SCOCG_C128)
         hipLaunchKernelGGL((k_gather_out<8, double2>), dim3(nbk), dim3(WG), 0, h->stream,
-                           S.x.as<double2>(), static_cast<double2*>(d), S.K, S.R, S.nS);
+                           S.x.as<double2>(), static_cast<double2*>(d), S.K, S.R, S.nS, S.sym);
       else
         hipLaunchKernelGGL((k_gather_out<8, float2>), dim3(nbk), dim3(WG), 0, h->stream,
-                           S.x.as<double2>(), static_cast<float2*>(d), S.K, S.R, S.nS);
+                           S.x.as<double2>(), static_cast<float2*>(d), S.K, S.R, S.nS, S.sym);
     } else {
       if (dtype == SCOCG_C128)
         hipLaunchKernelGGL((k_gather_out<16, double2>), dim3(nbk), dim3(WG), 0, h->stream,
-                           S.x.as<double2>(), static_cast<double2*>(d), S.K, S.R, S.nS);
+                           S.x.as<double2>(), static_cast<double2*>(d), S.K, S.R, S.nS, S.sym);
       else
         hipLaunchKernelGGL((k_gather_out<16, float2>), dim3(nbk), dim3(WG), 0, h->stream,
-                           S.x.as<double2>(), static_cast<float2*>(d), S.K, S.R, S.nS);
+                           S.x.as<double2>(), static_cast<float2*>(d), S.K, S.R, S.nS, S.sym);
     }
     KCHK();
     if (staged)

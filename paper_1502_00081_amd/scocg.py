@@ -39,7 +39,7 @@ class SolveOpts(C.Structure):
                 ("poll_every", C.c_int32), ("use_graph", C.c_int32), ("timing", C.c_int32),
                 ("tile", C.c_int32), ("zchunk", C.c_int32), ("shift_chunk", C.c_int32),
                 ("conventional", C.c_int32), ("aux_seed", C.c_int32),
-                ("seed_z", C.c_double * 2)]
+                ("seed_z", C.c_double * 2), ("symmetric", C.c_int32)]
 
 
 class Report(C.Structure):
@@ -131,7 +131,7 @@ def _dev_ptr(t):
 
 
 def _opts(tol, max_iter, init_seed, seed_switch, full, refine, poll_every, use_graph, timing,
-          tile, zchunk, shift_chunk, conventional=False, seed_z=None):
+          tile, zchunk, shift_chunk, conventional=False, seed_z=None, symmetric=False):
     o = SolveOpts(float(tol), int(max_iter), int(init_seed), int(bool(seed_switch)),
                   int(bool(full)), int(refine), int(poll_every), int(bool(use_graph)),
                   int(timing), int(tile), int(zchunk), int(shift_chunk),
@@ -139,6 +139,7 @@ def _opts(tol, max_iter, init_seed, seed_switch, full, refine, poll_every, use_g
     if seed_z is not None:
         o.aux_seed = 1
         o.seed_z[0], o.seed_z[1] = float(np.real(seed_z)), float(np.imag(seed_z))
+    o.symmetric = int(bool(symmetric))
     return o
 
 
@@ -172,16 +173,19 @@ class Handle:
 
     def solve(self, z, rhs_idx, s_idx=None, tol=1e-10, max_iter=100000, init_seed=-1,
               seed_switch=True, full=False, refine=0, poll_every=0, use_graph=False, timing=0,
-              tile=0, zchunk=0, shift_chunk=0, conventional=False, seed_z=None):
+              tile=0, zchunk=0, shift_chunk=0, conventional=False, seed_z=None,
+              symmetric=False):
         """scocg_solve; returns (rc, report dict with [K, R] arrays).  conventional=True runs
         every (energy, column) pair as its own recurrence (the comparison sweep).  seed_z (a
-        complex energy, not necessarily one of z) starts the seed recurrence there."""
+        complex energy, not necessarily one of z) starts the seed recurrence there.
+        symmetric=True (S = the RHS set) keeps each block's rows from its first column on
+        and mirrors the rest."""
         lib = load()
         z = _c(z, np.complex128)
         rhs = _c(rhs_idx, np.int64)
         sp = None if s_idx is None else _c(s_idx, np.int64)
         o = _opts(tol, max_iter, init_seed, seed_switch, full, refine, poll_every, use_graph,
-                  timing, tile, zchunk, shift_chunk, conventional, seed_z)
+                  timing, tile, zchunk, shift_chunk, conventional, seed_z, symmetric)
         rep, arrays = _new_report(z.size, rhs.size)
         rc = lib.scocg_solve(self._h, z.size, z.ctypes.data, rhs.size, rhs.ctypes.data,
                              0 if sp is None else sp.size,
@@ -297,7 +301,8 @@ def batch_solve(handles, problems, tol=1e-10, max_iter=100000, seed_switch=True,
 
 def open_boundary(handle, z, idx, M, L, sig_l, sig_r, tol=1e-10, max_iter=100000, device=None,
                   **solve_kw):
-    """Unperturbed columns on idx (scocg_solve), then the matching (scocg_obm).
+    """Unperturbed columns on idx (scocg_solve, symmetric rows by default), then the
+    matching (scocg_obm).
 
     idx = (left block, right block, extra rows) grid indices; sig_l, sig_r [K, M, M]
     complex (matrix orientation).  Returns a dict with the solve's rc and report, the
@@ -310,6 +315,7 @@ def open_boundary(handle, z, idx, M, L, sig_l, sig_r, tol=1e-10, max_iter=100000
     idx = np.asarray(idx, np.int64)
     K, D = z.size, idx.size
     assert D == 2 * M + L
+    solve_kw.setdefault("symmetric", True)
     rc, rep = handle.solve(z, idx, tol=tol, max_iter=max_iter, **solve_kw)
     g = torch.empty((K, D, D), dtype=torch.complex128, device=dev)
     handle.green_columns(out=g)

@@ -102,10 +102,12 @@ def check_against_oracle(p, M, L, out, sl, sr, tol):
         f"T = {np.round(out['T'].real, 4)}")
 
 
-@pytest.mark.parametrize("nx,ny,nz,K,extra", [(6, 6, 16, 6, True), (4, 5, 12, 5, False)])
+@pytest.mark.parametrize("nx,ny,nz,K,extra", [(6, 6, 16, 6, True), (4, 5, 12, 5, False),
+                                              (5, 5, 12, 4, True)])
 def test_obm_matches_direct_inversion(dev, nx, ny, nz, K, extra):
-    """Ragged tiles: M = 144 (two 64-row GEMM tiles and a tail), n = 288 (a 256-row
-    elimination tile and a tail), 36 extra rows; and a case without extra rows."""
+    """Ragged shapes: M = 144 (two 64-row GEMM tiles and a tail) with 36 extra rows; a
+    case without extra rows; and M = 100, n = 200 (six full 32-pivot panels and a last
+    panel of 8, GEMM tiles of 64 and 36) with 25 extra rows."""
     p, M, L = wire(nx, ny, nz, K, extra=extra)
     tol = 1e-11
     out, sl, sr = gpu_obm(p, M, L, dev, tol)

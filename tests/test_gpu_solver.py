@@ -667,3 +667,41 @@ def test_seed_at_an_energy_outside_the_sampled_set(dev):
         assert np.linalg.norm(G2 - ref, axis=2).max() <= 1e-8 * np.linalg.norm(ref, axis=2).min()
     finally:
         h.destroy()
+
+
+def test_symmetric_rows_mirror_the_full_projected_result(dev):
+    """symmetric = 1 with S = the RHS set: entries a block keeps (rows from its first
+    column on) are bitwise those of the plain solve, the mirrored ones agree within the
+    two columns' error bounds (tol / eta each); FP64 (blocks of 8) and complex64 (blocks
+    of 16).  Mixing it with explicit rows, full storage or the conventional sweep is
+    rejected."""
+    p = small(8, 8, 12, 4, True, K=6, nb=10, nt=10)
+    R = p.rhs_idx.size
+    tol = 1e-10
+    eta = p.z.imag.min()
+    for prec, B, bound in ((scocg.FP64, 8, 2 * tol / eta), (scocg.MIXED, 16, 1e-3)):
+        h = scocg.create_from_problem(p, precision=prec)
+        try:
+            rc, _ = h.solve(p.z, p.rhs_idx, tol=tol if prec == scocg.FP64 else 1e-5)
+            G = h.green_columns()
+            rc2, _ = h.solve(p.z, p.rhs_idx, tol=tol if prec == scocg.FP64 else 1e-5,
+                             symmetric=True)
+            Gs = h.green_columns()
+            if prec == scocg.FP64:
+                assert rc == scocg.OK and rc2 == scocg.OK
+            j = np.arange(R)[None, :, None]
+            i = np.arange(R)[None, None, :]
+            kept = np.broadcast_to(i >= (j // B) * B, G.shape)
+            assert np.array_equal(Gs[kept], G[kept])
+            d = np.abs(Gs - G)[~kept].max()
+            scale = np.abs(G).max() if prec == scocg.MIXED else 1.0
+            assert d <= bound * scale, (prec, d)
+            say(f"symmetric rows, precision {prec}: mirrored entries differ by {d:.2e}")
+            with pytest.raises(scocg.ScocgError):
+                h.solve(p.z, p.rhs_idx, s_idx=p.rhs_idx, symmetric=True)
+            with pytest.raises(scocg.ScocgError):
+                h.solve(p.z, p.rhs_idx, full=True, symmetric=True)
+            with pytest.raises(scocg.ScocgError):
+                h.solve(p.z, p.rhs_idx, conventional=True, symmetric=True)
+        finally:
+            h.destroy()
