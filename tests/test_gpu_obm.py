@@ -182,3 +182,26 @@ def test_obm_argument_errors_and_breakdown(dev):
         assert np.all(np.isfinite(out["T"]))
     finally:
         h.destroy()
+
+
+def test_obm_without_output_buffer_and_repeat(dev):
+    """gt_dev = NULL (the library keeps G_T in its own workspace): T and DOS equal those of
+    a call with an output buffer bit for bit, and a second call on the same inputs repeats
+    them exactly (fixed reduction order)."""
+    p, M, L = wire(5, 4, 10, 3)
+    h = scocg.create_from_problem(p, precision=scocg.FP64)
+    try:
+        sl, sr = W.lead_self_energies(p.nx, p.ny, p.coef, p.z)
+        out = scocg.open_boundary(h, p.z, p.rhs_idx, M, L, sl, sr, tol=1e-11, device=dev)
+        K, D = p.z.size, p.rhs_idx.size
+        g = torch.from_numpy(np.ascontiguousarray(out["g"].transpose(0, 2, 1))).to(dev)
+        slt = torch.from_numpy(np.ascontiguousarray(sl.transpose(0, 2, 1))).to(dev)
+        srt = torch.from_numpy(np.ascontiguousarray(sr.transpose(0, 2, 1))).to(dev)
+        torch.cuda.synchronize()
+        rc1, T1, d1 = h.obm(K, M, L, g, slt, srt, None)
+        rc2, T2, d2 = h.obm(K, M, L, g, slt, srt, None)
+        assert rc1 == rc2 == scocg.OK
+        assert np.array_equal(T1, out["T"]) and np.array_equal(d1, out["dos"])
+        assert np.array_equal(T1, T2) and np.array_equal(d1, d2)
+    finally:
+        h.destroy()
