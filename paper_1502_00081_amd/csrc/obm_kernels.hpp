@@ -170,50 +170,71 @@ __global__ __launch_bounds__(GJ_PNT) void k_gj_panel(double2* W, double2* F, dou
   if (fail[k]) return;
   double2* Wk = W + (size_t)k * n * ncol;
   double2* Fk = F + (size_t)k * n * GJ_W;
-  __shared__ double s_val[GJ_PNT];
-  __shared__ int s_idx[GJ_PNT];
+  __shared__ double s_val[GJ_PNT / 64];
+  __shared__ int s_idx[GJ_PNT / 64];
+  __shared__ double2 s_prow[GJ_W];  // row j over the panel columns, after the swap
   const int tid = threadIdx.x;
   const int jend = j0 + w;
+  // pivot candidates of the first column; later columns' candidates are taken while
+  // the previous pivot is eliminated
+  double best = -1.0;
+  int bi = n;
+  for (int i = j0 + tid; i < n; i += GJ_PNT) {
+    const double a = cabs2(Wk[i + (size_t)n * j0]);
+    if (a > best) {  // strict: the smallest index of this thread's rows on ties
+      best = a;
+      bi = i;
+    }
+  }
+  constexpr int NWAVE = GJ_PNT / 64;
   for (int jj = 0; jj < w; ++jj) {
     const int j = j0 + jj;
-    double best = -1.0;
-    int bi = n;
-    for (int i = j + tid; i < n; i += GJ_PNT) {
-      const double a = cabs2(Wk[i + (size_t)n * j]);
-      if (a > best) {
-        best = a;
-        bi = i;
+    // argmax (largest |W(i, j)|^2, smallest i on ties): across the 64 lanes of each
+    // wave by shuffles, then across the waves in LDS
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double o = __shfl_xor(best, off);
+      const int oi = __shfl_xor(bi, off);
+      if (o > best || (o == best && oi < bi)) {
+        best = o;
+        bi = oi;
       }
     }
-    s_val[tid] = best;
-    s_idx[tid] = bi;
+    if ((tid & 63) == 0) {
+      s_val[tid >> 6] = best;
+      s_idx[tid >> 6] = bi;
+    }
     __syncthreads();
-    for (int st = GJ_PNT / 2; st > 0; st >>= 1) {
-      if (tid < st) {
-        const double o = s_val[tid + st];
-        const int oi = s_idx[tid + st];
-        if (o > s_val[tid] || (o == s_val[tid] && oi < s_idx[tid])) {
-          s_val[tid] = o;
-          s_idx[tid] = oi;
-        }
+    double pv = s_val[0];
+    int p = s_idx[0];
+#pragma unroll
+    for (int q = 1; q < NWAVE; ++q) {
+      const double o = s_val[q];
+      const int oi = s_idx[q];
+      if (o > pv || (o == pv && oi < p)) {
+        pv = o;
+        p = oi;
       }
-      __syncthreads();
     }
-    const int p = s_idx[0];
-    const double pv = s_val[0];
-    __syncthreads();  // everyone has read the result before the arrays are reused
     if (!(pv > 0.0) || !isfinite(pv) || p >= n) {
       if (tid == 0) fail[k] = 1;
       return;
     }
-    if (p != j) {
-      for (int c = j + tid; c < ncol; c += GJ_PNT) {
-        double2* a = Wk + j + (size_t)n * c;
+    // swap rows j and p from column j on; the threads of the panel columns keep the
+    // new row j for everyone
+    for (int c = j + tid; c < ncol; c += GJ_PNT) {
+      double2* a = Wk + j + (size_t)n * c;
+      double2 v = *a;
+      if (p != j) {
         double2* b = Wk + p + (size_t)n * c;
-        const double2 t = *a;
-        *a = *b;
+        const double2 t = v;
+        v = *b;
+        *a = v;
         *b = t;
       }
+      if (c < jend) s_prow[c - j0] = v;
+    }
+    if (p != j)
       for (int c = tid; c < jj; c += GJ_PNT) {
         double2* a = Fk + j + (size_t)n * c;
         double2* b = Fk + p + (size_t)n * c;
@@ -221,34 +242,40 @@ __global__ __launch_bounds__(GJ_PNT) void k_gj_panel(double2* W, double2* F, dou
         *a = *b;
         *b = t;
       }
-    }
     __syncthreads();
-    const double2 piv = Wk[j + (size_t)n * j];
-    for (int i = tid; i < n; i += GJ_PNT)
-      Fk[i + (size_t)n * jj] = (i == j) ? double2{0.0, 0.0} : Wk[i + (size_t)n * j];
-    if (tid == 0) pivv[(size_t)k * GJ_W + jj] = piv;
-    __syncthreads();  // column j read before row j is rescaled
+    const double2 piv = s_prow[jj];
     const double inv_den = 1.0 / cabs2(piv);
     const double2 inv = {piv.x * inv_den, -piv.y * inv_den};
-    for (int c = j + 1 + tid; c < jend; c += GJ_PNT) {
-      double2* a = Wk + j + (size_t)n * c;
-      *a = cmul(*a, inv);
+    if (tid == 0) pivv[(size_t)k * GJ_W + jj] = piv;
+    // every row i: multiplier f_i = W(i, j) (0 for i = j), then the panel columns
+    // right of j: row j scaled by 1/pivot, other rows minus f_i times that
+    best = -1.0;
+    bi = n;
+    for (int i = tid; i < n; i += GJ_PNT) {
+      const double2 fi = (i == j) ? double2{0.0, 0.0} : Wk[i + (size_t)n * j];
+      Fk[i + (size_t)n * jj] = fi;
+      for (int c = j + 1; c < jend; ++c) {
+        const double2 pj = cmul(s_prow[c - j0], inv);
+        double2* a = Wk + i + (size_t)n * c;
+        double2 v;
+        if (i == j) {
+          v = pj;
+        } else {
+          v = *a;
+          v.x = fma(-fi.x, pj.x, fma(fi.y, pj.y, v.x));
+          v.y = fma(-fi.x, pj.y, fma(-fi.y, pj.x, v.y));
+        }
+        *a = v;
+        if (c == j + 1 && i > j) {
+          const double m = cabs2(v);
+          if (m > best) {
+            best = m;
+            bi = i;
+          }
+        }
+      }
     }
-    __syncthreads();
-    // eliminate inside the panel: rows i != j, columns j+1 .. jend-1
-    const int pc = jend - j - 1;
-    for (int e = tid; e < n * pc; e += GJ_PNT) {
-      const int i = e % n, c = j + 1 + e / n;
-      if (i == j) continue;
-      const double2 fi = Fk[i + (size_t)n * jj];
-      const double2 pj = Wk[j + (size_t)n * c];
-      double2* a = Wk + i + (size_t)n * c;
-      double2 v = *a;
-      v.x = fma(-fi.x, pj.x, fma(fi.y, pj.y, v.x));
-      v.y = fma(-fi.x, pj.y, fma(-fi.y, pj.x, v.y));
-      *a = v;
-    }
-    __syncthreads();
+    __syncthreads();  // s_prow, s_val and this step's writes are settled before the next step
   }
 }
 
@@ -307,8 +334,10 @@ __global__ __launch_bounds__(256) void k_gj_update(double2* W, const double2* __
       acc[c] = in_panel ? zs[i - j0][c]
                         : (c < nc ? Wk[i + (size_t)n * (c0 + c)] : double2{0.0, 0.0});
     const int jstart = in_panel ? i - j0 + 1 : 0;
+    double2 fnext = jstart < w ? Fk[i + (size_t)n * jstart] : double2{0.0, 0.0};
     for (int jp = jstart; jp < w; ++jp) {
-      const double2 f = Fk[i + (size_t)n * jp];
+      const double2 f = fnext;
+      if (jp + 1 < w) fnext = Fk[i + (size_t)n * (jp + 1)];  // next multiplier in flight
 #pragma unroll
       for (int c = 0; c < GJ_CW; ++c) {
         const double2 zz = zs[jp][c];
