@@ -344,6 +344,25 @@ def obm_run(a):
     print(json.dumps(obm_measure(a, a.steps, a.warmup)), flush=True)
 
 
+def copy_bandwidth(nbytes=1 << 30, reps=5):
+    """Achievable HBM bandwidth on this GPU: a plain device-to-device copy of nbytes,
+    timed with HIP events over reps copies; bytes read + written per second (GB/s)."""
+    import torch
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    del src, dst
+    return 2.0 * nbytes * reps / (ms * 1e-3) / 1e9
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -441,7 +460,9 @@ def main():
                      "traffic_note": None if traffic is None else
                      f"HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated) over "
                      f"launches whose algorithmic bytes are {traffic_alg:.4g}: ratio "
-                     f"{traffic / traffic_alg:.3f}"},
+                     f"{traffic / traffic_alg:.3f}",
+                     "hbm_gbs_from_counters": None if traffic is None else
+                     achieved * traffic / traffic_alg},
         "launch_shape": {"tile": reps[-1]["tile"], "zchunk": reps[-1]["zchunk"],
                          "shift_chunk": reps[-1]["shift_chunk"],
                          "autotuned": not a.fixed_shape},
@@ -465,6 +486,15 @@ def main():
         line["ms_per_step_graph_replay"] = (time.perf_counter() - tg) * 1e3
     h.destroy()
     del out
+    # achievable bandwidth of this GPU (plain copy), and the r_{n+1} pass against it
+    bw = copy_bandwidth()
+    rf = line["roofline"]
+    rf["achievable_copy_gbs"] = bw
+    rf["frac_of_achievable"] = rf["achieved"] / bw
+    if rf["hbm_gbs_from_counters"] is not None:
+        rf["counters_frac_of_achievable"] = rf["hbm_gbs_from_counters"] / bw
+    say(f"copy kernel: {bw:.0f} GB/s achievable; r_(n+1) pass {rf['achieved']:.0f} GB/s "
+        f"algorithmic = {rf['frac_of_achievable']:.1%} of it")
     if not a.no_mixed:
         line["mixed_vs_fp64"] = mixed_vs_fp64(a.tol)
     if not a.no_obm:
