@@ -271,7 +271,7 @@ def create_from_problem(p, precision=FP64, stream=None) -> Handle:
 
 def batch_solve(handles, problems, tol=1e-10, max_iter=100000, seed_switch=True, full=False,
                 refine=0, poll_every=0, use_graph=False, timing=0, tile=0, zchunk=0,
-                shift_chunk=0):
+                shift_chunk=0, symmetric=False):
     """scocg_batch_solve over regions; problems: [(z, rhs_idx) or (z, rhs_idx, s_idx)].
     Returns (rc, [report dict per region], region_ms [n])."""
     lib = load()
@@ -292,7 +292,7 @@ def batch_solve(handles, problems, tol=1e-10, max_iter=100000, seed_switch=True,
         handles[i].last = (z.size, rhs.size, nrows)
     hs = (C.c_void_p * n)(*[h._h.value for h in handles])
     o = _opts(tol, max_iter, -1, seed_switch, full, refine, poll_every, use_graph, timing, tile,
-              zchunk, shift_chunk)
+              zchunk, shift_chunk, symmetric=symmetric)
     region_ms = np.zeros(n)
     rc = lib.scocg_batch_solve(n, hs, probs, C.byref(o), reps, region_ms.ctypes.data)
     _check(rc)

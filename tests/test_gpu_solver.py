@@ -705,3 +705,37 @@ def test_symmetric_rows_mirror_the_full_projected_result(dev):
                 h.solve(p.z, p.rhs_idx, conventional=True, symmetric=True)
         finally:
             h.destroy()
+
+
+def test_symmetric_rows_in_a_batch_and_aux_seed_with_complex64(dev):
+    """symmetric rows in a batched solve give bit for bit the single symmetric solves; an
+    auxiliary seed with complex64 vectors (full storage, refinement) certifies every
+    sampled pair against its FP64 true residual and returns only the sampled energies."""
+    regs = [small(8, 8, 10, 4, False, K=4, nb=6, nt=5, seed=3),
+            small(8, 8, 14, 4, True, K=7, nb=9, nt=9, seed=4)]
+    stream = torch.cuda.Stream()
+    hs = [scocg.create_from_problem(p, precision=scocg.FP64, stream=stream) for p in regs]
+    try:
+        single = []
+        for h, p in zip(hs, regs):
+            rc, rep = h.solve(p.z, p.rhs_idx, tol=1e-10, symmetric=True)
+            single.append(h.green_columns())
+        rc, reps, _ = scocg.batch_solve(hs, [(p.z, p.rhs_idx) for p in regs], tol=1e-10,
+                                        symmetric=True)
+        assert rc == scocg.OK
+        for h, G1 in zip(hs, single):
+            assert np.array_equal(h.green_columns(), G1)
+    finally:
+        for h in hs:
+            h.destroy()
+    p = small(8, 8, 12, 4, True, K=5)
+    h = scocg.create_from_problem(p, precision=scocg.MIXED)
+    try:
+        rc, rep = h.solve(p.z, p.rhs_idx, tol=1e-8, full=True, refine=3, seed_z=0.05 + 0.3j)
+        assert rc == scocg.OK, rep["status"]
+        assert (rep["true_resid"] <= 1e-8).all()
+        G = h.green_columns()
+        assert G.shape == (p.z.size, p.rhs_idx.size, p.n)
+        assert (true_residuals(p, G) <= 1.5e-8).all()
+    finally:
+        h.destroy()
