@@ -309,22 +309,22 @@ __global__ __launch_bounds__(256) void k_gj_update(double2* W, const double2* __
     pinv[tid] = {pv.x * d, -pv.y * d};
   }
   __syncthreads();
-  // forward sweep over the panel's pivots
-  for (int jj = 0; jj < w; ++jj) {
-    if (tid < GJ_CW) zs[jj][tid] = cmul(zs[jj][tid], pinv[jj]);
-    __syncthreads();
-    const int rows = w - jj - 1;
-    for (int e = tid; e < rows * GJ_CW; e += 256) {
-      const int i = jj + 1 + e % rows, c = e / rows;
-      double2 v = zs[i][c];
-      const double2 f = fj[i][jj];
-      const double2 zz = zs[jj][c];
-      v.x = fma(-f.x, zz.x, fma(f.y, zz.y, v.x));
-      v.y = fma(-f.x, zz.y, fma(-f.y, zz.x, v.y));
-      zs[i][c] = v;
+  // forward sweep over the panel's pivots, one thread per column (no barriers; the
+  // subtractions of each z_j come in the order j' = 0, 1, ... as in the elimination)
+  if (tid < GJ_CW) {
+    const int c = tid;
+    for (int jj = 0; jj < w; ++jj) {
+      double2 v = zs[jj][c];
+      for (int jp = 0; jp < jj; ++jp) {
+        const double2 f = fj[jj][jp];
+        const double2 zz = zs[jp][c];
+        v.x = fma(-f.x, zz.x, fma(f.y, zz.y, v.x));
+        v.y = fma(-f.x, zz.y, fma(-f.y, zz.x, v.y));
+      }
+      zs[jj][c] = cmul(v, pinv[jj]);
     }
-    __syncthreads();
   }
+  __syncthreads();
   // every row: rows of the panel from z with the upper multipliers, others rank-w update
   for (int i = tid; i < n; i += 256) {
     const bool in_panel = i >= j0 && i < j0 + w;
