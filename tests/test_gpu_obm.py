@@ -114,6 +114,15 @@ def test_obm_matches_direct_inversion(dev, nx, ny, nz, K, extra):
     check_against_oracle(p, M, L, out, sl, sr, tol)
 
 
+def test_obm_wide_boundary_many_panels(dev):
+    """A wider boundary: 13x11 planes, M = 572, n = 1144 (35 full 32-pivot panels and a
+    last one of 24; GEMM tiles of 64 and a 60-row tail), 143 extra rows, 1287 columns."""
+    p, M, L = wire(13, 11, 24, 2)
+    tol = 1e-11
+    out, sl, sr = gpu_obm(p, M, L, dev, tol)
+    check_against_oracle(p, M, L, out, sl, sr, tol)
+
+
 def test_obm_full_wire_workload(dev):
     """The benchmarked configuration (8x8x32, M = 256, L = 64, 16 energies) end to end."""
     p, M, L = W.obm_wire()
