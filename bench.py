@@ -267,14 +267,16 @@ def obm_cpu_baseline(p, M, sl, sr, n_energies=2):
                       f"Eq. 13 matrix with {p.rhs_idx.size} right-hand sides each"}
 
 
-def obm_measure(a, steps, warmup):
+def obm_measure(a, steps, warmup, wide=False):
     """Open-boundary matching on the 8x8x32 scatterer wire (M = 256 rows per boundary
-    block, 64 extra rows of the middle plane, 16 energies in [0.1, 3.0] Ha): the
+    block, 64 extra rows of the middle plane, 16 energies in [0.1, 3.0] Ha; wide: the
+    16x16x32 wire, M = 1024, 256 extra rows): the
     unperturbed columns on the 576 boundary and extra rows (shifted COCG, tol 1e-10),
     then the matching, transmission and density of states (scocg_obm)."""
     import torch
     from paper_1502_00081_amd import scocg, workload
-    p, M, L = workload.obm_wire()
+    # wide: 16x16x32 (M = 1024, 2304 columns); the dense CPU oracle is skipped there
+    p, M, L = workload.obm_wire(nx=16, ny=16) if wide else workload.obm_wire()
     K, D, n = p.z.size, p.rhs_idx.size, 2 * M
     dev = torch.device("cuda", 0)
     sl, sr = workload.lead_self_energies(p.nx, p.ny, p.coef, p.z)
@@ -320,7 +322,7 @@ def obm_measure(a, steps, warmup):
     upd_flops = K * sum(8 * w * n * (ncol - j0 - w) for j0, w in panels)
     upd_bytes = K * sum(32 * n * (ncol - j0 - w) for j0, w in panels)
     cpu = None
-    if not a.no_cpu_baseline:
+    if not a.no_cpu_baseline and not wide:
         cpu = obm_cpu_baseline(p, M, sl, sr)
     return {
         "metric": "transmission + DOS energies/s (unperturbed solve + open-boundary matching)",
@@ -340,8 +342,8 @@ def obm_measure(a, steps, warmup):
         "T": [round(float(x), 6) for x in T.real], "dos": [round(float(x), 6) for x in dos]}
 
 
-def obm_run(a):
-    print(json.dumps(obm_measure(a, a.steps, a.warmup)), flush=True)
+def obm_run(a, wide=False):
+    print(json.dumps(obm_measure(a, a.steps, a.warmup, wide)), flush=True)
 
 
 def copy_bandwidth(nbytes=1 << 30, reps=5):
@@ -379,8 +381,8 @@ def main():
     if a.workload == "sweep":
         sweep_run(a)
         return
-    if a.workload == "obm_wire":
-        obm_run(a)
+    if a.workload in ("obm_wire", "obm_wide"):
+        obm_run(a, wide=a.workload == "obm_wide")
         return
     p = workload.WORKLOADS[a.workload]()
     prec = scocg.FP64 if a.precision == "fp64" else scocg.MIXED
