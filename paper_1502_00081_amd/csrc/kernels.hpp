@@ -159,6 +159,7 @@ struct ShiftArgs {
   int gx, gy;                 // workgroups per block along rows and along the list
   int kch;                    // list entries (energies) per workgroup
   int sym;                    // 1: S is the RHS set and block cb keeps rows i >= cb*B only
+  int nt;                     // 1: x, p outgrow the last-level cache; stream them nontemporally
 };
 
 template <typename T>
@@ -1121,6 +1122,41 @@ __global__ __launch_bounds__(CT) void k_control(const ControlArgs* __restrict__ 
 // grid: (ceil(nS*B/WG), ceil(K/KCH), nb); each thread owns one (row of S, column)
 // and walks a chunk of the block's active shift list.
 
+// The energy loop of one thread (row i of S, column c): x, p updates of the list
+// entries e0..e1-1.  NT: nontemporal x, p (they do not fit the last-level cache).
+template <bool NT, int B, typename T>
+__device__ __forceinline__ void shift_loop(const ShiftArgs<T>& a, const int32_t* l, int e0,
+                                           int e1, int cb, int i, int c, double2 rv) {
+  using cT = typename cplx_of<T>::type;
+  const int nS = a.nS, K = a.K;
+  double2* __restrict__ x = a.x;
+  cT* __restrict__ p = a.p;
+  for (int e = e0; e < e1; ++e) {
+    const int k = l[e];
+    const int64_t so = ((int64_t)cb * K + k) * B + c;
+    const ShiftCoef cf = a.coef[so];
+    if (!cf.upd) continue;
+    const int64_t vo = (((int64_t)cb * K + k) * nS + i) * B + c;
+    const double2 xv = NT ? ld_stream(x + vo) : x[vo];
+    const double2 pv = to_d(NT ? ld_stream(p + vo) : p[vo]);
+    // explicit FMAs: both instances (and full and projected storage) round alike
+    double2 xn, t, pn;
+    xn.x = __builtin_fma(cf.a.x, pv.x, __builtin_fma(-cf.a.y, pv.y, xv.x));
+    xn.y = __builtin_fma(cf.a.x, pv.y, __builtin_fma(cf.a.y, pv.x, xv.y));
+    t.x = __builtin_fma(cf.b.x, pv.x, -(cf.b.y * pv.y));
+    t.y = __builtin_fma(cf.b.x, pv.y, cf.b.y * pv.x);
+    pn.x = __builtin_fma(cf.f.x, rv.x, __builtin_fma(-cf.f.y, rv.y, t.x));
+    pn.y = __builtin_fma(cf.f.x, rv.y, __builtin_fma(cf.f.y, rv.x, t.y));
+    if (NT) {
+      st_stream(x + vo, xn);
+      st_stream(p + vo, from_d<cT>(pn));
+    } else {
+      x[vo] = xn;
+      p[vo] = from_d<cT>(pn);
+    }
+  }
+}
+
 // x^(k) += alpha^(k) p^(k);  p^(k) = r_{n+1}[S] / pi^(k)_{n+1} + beta^(k) p^(k)  (Eqs. A11-A12)
 // for workgroup lb of one region (NTH threads): gx * gy * nb workgroups, NTH rows of S
 // x kch list entries x column block.  par: parity of the iteration being completed.
@@ -1143,19 +1179,10 @@ __device__ __forceinline__ void shift_body(const ShiftArgs<T>& a, int lb, int pa
   const cT* rnew = par ? a.rnew[0] : a.rnew[1];  // r_{n+1}: buffer par ^ 1
   const double2 rv = to_d(rnew[(int64_t)cb * a.bstride + row * B + c]);
   const int32_t* l = a.list + ((int64_t)par * a.nb + cb) * K;
-  double2* __restrict__ x = a.x;
-  cT* __restrict__ p = a.p;
-  for (int e = e0; e < e1; ++e) {
-    const int k = l[e];
-    const int64_t so = ((int64_t)cb * K + k) * B + c;
-    const ShiftCoef cf = a.coef[so];
-    if (!cf.upd) continue;
-    const int64_t vo = (((int64_t)cb * K + k) * nS + i) * B + c;
-    const double2 xv = x[vo];
-    const double2 pv = to_d(p[vo]);
-    x[vo] = cadd(xv, cmul(cf.a, pv));
-    p[vo] = from_d<cT>(cadd(cmul(cf.f, rv), cmul(cf.b, pv)));
-  }
+  if (a.nt)
+    shift_loop<true, B, T>(a, l, e0, e1, cb, i, c, rv);
+  else
+    shift_loop<false, B, T>(a, l, e0, e1, cb, i, c, rv);
 }
 
 // Stand-alone x, p update of the last iteration of a solve (every other iteration's

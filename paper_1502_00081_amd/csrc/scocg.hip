@@ -356,6 +356,9 @@ struct Solver {
     sa.gy = (int)nblocks(S.K, kch);
     sa.kch = kch;
     sa.sym = S.sym;
+    // x (complex128) and p together beyond the 256 MB last-level cache: nontemporal
+    const double xp_bytes = (double)S.nb * S.K * S.nS * B * (16.0 + sizeof(cT));
+    sa.nt = xp_bytes > 256.0 * (1 << 20);
     return sa;
   }
 
