@@ -7,7 +7,7 @@
  *     x^{(k)}_j = [Z_k - H]^{-1} e_j ,   Z_k = E_k + i*eta ,
  *
  * of the unperturbed Green's function (Sec. 3B, Eq. 17), restricted to a set S
- * of output rows ("the required elements", Appendix after Eq. A12).  One seed
+ * of output rows (only those elements are kept, Appendix after Eq. A12).  One seed
  * Krylov recurrence per right-hand side e_j serves every energy Z_k: the
  * shifted COCG method with collinear residuals (Appendix, Eqs. A7-A12) and
  * seed switching (Eq. A13).
