@@ -160,12 +160,14 @@ __global__ __launch_bounds__(256) void k_obm_init(const double2* __restrict__ g,
 // so each column is read and written once per panel instead of once per pivot.
 // A zero or non-finite pivot marks the energy failed; later kernels skip it.
 constexpr int GJ_W = 32;     // pivots per panel
-constexpr int GJ_CW = 16;    // columns per workgroup of the update
 constexpr int GJ_PNT = 512;  // threads of the panel kernel
 
+// Vj [K][GJ_W][ncol]: row j0 + jj of every column right of the panel, as it stands
+// once its swap is done (its final row order); the update reads its sweep input
+// from here, so the tile that owns the panel rows can overwrite them in W.
 __global__ __launch_bounds__(GJ_PNT) void k_gj_panel(double2* W, double2* F, double2* pivv,
-                                                     int32_t* fail, int n, int ncol, int j0,
-                                                     int w) {
+                                                     double2* Vj, int32_t* fail, int n,
+                                                     int ncol, int j0, int w) {
   const int k = blockIdx.x;
   if (fail[k]) return;
   double2* Wk = W + (size_t)k * n * ncol;
@@ -232,7 +234,10 @@ __global__ __launch_bounds__(GJ_PNT) void k_gj_panel(double2* W, double2* F, dou
         *a = v;
         *b = t;
       }
-      if (c < jend) s_prow[c - j0] = v;
+      if (c < jend)
+        s_prow[c - j0] = v;
+      else
+        Vj[((size_t)k * GJ_W + jj) * ncol + c] = v;
     }
     if (p != j)
       for (int c = tid; c < jj; c += GJ_PNT) {
@@ -279,27 +284,22 @@ __global__ __launch_bounds__(GJ_PNT) void k_gj_panel(double2* W, double2* F, dou
   }
 }
 
-// grid = (column groups of GJ_CW over columns j0+w .. ncol-1, energies), 256 threads.
-__global__ __launch_bounds__(256) void k_gj_update(double2* W, const double2* __restrict__ F,
-                                                   const double2* __restrict__ pivv,
-                                                   const int32_t* __restrict__ fail, int n,
-                                                   int ncol, int j0, int w) {
+// Forward sweep of the panel rows of every column right of the panel, in place in
+// Vj (one thread per column; the subtractions of each z_j in the order j' = 0, 1, ...
+// of the elimination):
+//   z_j = (v_j - sum_{j' < j} f^(j')_j z_j') / pivot_j
+// grid = (column groups of 64 over columns j0+w .. ncol-1, energies), 64 threads.
+__global__ __launch_bounds__(64) void k_gj_sweep(double2* Vj, const double2* __restrict__ F,
+                                                 const double2* __restrict__ pivv,
+                                                 const int32_t* __restrict__ fail, int n,
+                                                 int ncol, int j0, int w) {
   const int k = blockIdx.y;
   if (fail[k]) return;
-  const int c0 = j0 + w + blockIdx.x * GJ_CW;
-  if (c0 >= ncol) return;
-  const int nc = min(GJ_CW, ncol - c0);
-  double2* Wk = W + (size_t)k * n * ncol;
-  const double2* Fk = F + (size_t)k * n * GJ_W;
-  __shared__ double2 zs[GJ_W][GJ_CW];
   __shared__ double2 fj[GJ_W][GJ_W + 1];  // fj[i][j'] = f^(j')_{j0+i}
   __shared__ double2 pinv[GJ_W];
+  const double2* Fk = F + (size_t)k * n * GJ_W;
   const int tid = threadIdx.x;
-  for (int e = tid; e < w * GJ_CW; e += 256) {
-    const int i = e % w, c = e / w;
-    zs[i][c] = c < nc ? Wk[(j0 + i) + (size_t)n * (c0 + c)] : double2{0.0, 0.0};
-  }
-  for (int e = tid; e < w * w; e += 256) {
+  for (int e = tid; e < w * w; e += 64) {
     const int i = e % w, jp = e / w;
     fj[i][jp] = Fk[(j0 + i) + (size_t)n * jp];
   }
@@ -309,45 +309,101 @@ __global__ __launch_bounds__(256) void k_gj_update(double2* W, const double2* __
     pinv[tid] = {pv.x * d, -pv.y * d};
   }
   __syncthreads();
-  // forward sweep over the panel's pivots, one thread per column (no barriers; the
-  // subtractions of each z_j come in the order j' = 0, 1, ... as in the elimination)
-  if (tid < GJ_CW) {
-    const int c = tid;
-    for (int jj = 0; jj < w; ++jj) {
-      double2 v = zs[jj][c];
+  const int c = j0 + w + blockIdx.x * 64 + tid;
+  if (c >= ncol) return;
+  double2* col = Vj + (size_t)k * GJ_W * ncol + c;
+  double2 z[GJ_W];
+#pragma unroll
+  for (int jj = 0; jj < GJ_W; ++jj) z[jj] = jj < w ? col[(size_t)jj * ncol] : double2{0.0, 0.0};
+#pragma unroll
+  for (int jj = 0; jj < GJ_W; ++jj) {
+    if (jj < w) {  // a predicate, not a break: every index of z stays a constant
+      double2 v = z[jj];
+#pragma unroll
       for (int jp = 0; jp < jj; ++jp) {
         const double2 f = fj[jj][jp];
-        const double2 zz = zs[jp][c];
-        v.x = fma(-f.x, zz.x, fma(f.y, zz.y, v.x));
-        v.y = fma(-f.x, zz.y, fma(-f.y, zz.x, v.y));
+        v.x = fma(-f.x, z[jp].x, fma(f.y, z[jp].y, v.x));
+        v.y = fma(-f.x, z[jp].y, fma(-f.y, z[jp].x, v.y));
       }
-      zs[jj][c] = cmul(v, pinv[jj]);
+      z[jj] = cmul(v, pinv[jj]);
+      col[(size_t)jj * ncol] = z[jj];
     }
   }
+}
+
+// Update of the columns right of the panel as a tiled product: workgroup (column tile,
+// row tile, energy) owns a GJ_T x GJ_T tile of W.  With the swept panel rows z of its
+// columns (Vj) and the multiplier rows of its tile in LDS -- the lower multipliers of
+// the panel rows zeroed, so those rows start from z and take only the upper terms --
+// each thread updates 4 x 4 elements:
+//   rows of the panel:  z_j - sum_{j' > j} f^(j')_j z_j';   other rows:  v_i - sum_j' f^(j')_i z_j'.
+// Subtracting a zeroed term leaves a finite value bit for bit unchanged, so this equals
+// the row-by-row update.
+constexpr int GJ_T = 64;  // rows and columns per workgroup tile of the update
+
+__global__ __launch_bounds__(256) void k_gj_update(double2* W, const double2* __restrict__ F,
+                                                   const double2* __restrict__ Vj,
+                                                   const int32_t* __restrict__ fail, int n,
+                                                   int ncol, int j0, int w) {
+  const int k = blockIdx.z;
+  if (fail[k]) return;
+  const int c0 = j0 + w + blockIdx.x * GJ_T;
+  const int r0 = blockIdx.y * GJ_T;
+  if (c0 >= ncol || r0 >= n) return;
+  double2* Wk = W + (size_t)k * n * ncol;
+  const double2* Fk = F + (size_t)k * n * GJ_W;
+  __shared__ double2 zs[GJ_W][GJ_T + 1];  // swept panel rows of the tile's columns
+  __shared__ double2 fs[GJ_T][GJ_W + 1];  // multipliers of the tile's rows
+  const int tid = threadIdx.x;
+  for (int e = tid; e < w * GJ_T; e += 256) {
+    const int c = e % GJ_T, i = e / GJ_T;
+    zs[i][c] = c0 + c < ncol ? Vj[((size_t)k * GJ_W + i) * ncol + c0 + c] : double2{0.0, 0.0};
+  }
+  for (int e = tid; e < GJ_T * GJ_W; e += 256) {
+    const int r = e % GJ_T, jp = e / GJ_T;
+    const int i = r0 + r;
+    double2 f = {0.0, 0.0};
+    // panel rows take only the multipliers of later pivots
+    if (i < n && jp < w && !(i >= j0 && i < j0 + w && jp <= i - j0)) f = Fk[i + (size_t)n * jp];
+    fs[r][jp] = f;
+  }
   __syncthreads();
-  // every row: rows of the panel from z with the upper multipliers, others rank-w update
-  for (int i = tid; i < n; i += 256) {
+  const int tx = tid & 15, ty = tid >> 4;
+  double2 acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int i = r0 + tx + 16 * a;
     const bool in_panel = i >= j0 && i < j0 + w;
-    double2 acc[GJ_CW];
 #pragma unroll
-    for (int c = 0; c < GJ_CW; ++c)
-      acc[c] = in_panel ? zs[i - j0][c]
-                        : (c < nc ? Wk[i + (size_t)n * (c0 + c)] : double2{0.0, 0.0});
-    const int jstart = in_panel ? i - j0 + 1 : 0;
-    double2 fnext = jstart < w ? Fk[i + (size_t)n * jstart] : double2{0.0, 0.0};
-    for (int jp = jstart; jp < w; ++jp) {
-      const double2 f = fnext;
-      if (jp + 1 < w) fnext = Fk[i + (size_t)n * (jp + 1)];  // next multiplier in flight
-#pragma unroll
-      for (int c = 0; c < GJ_CW; ++c) {
-        const double2 zz = zs[jp][c];
-        acc[c].x = fma(-f.x, zz.x, fma(f.y, zz.y, acc[c].x));
-        acc[c].y = fma(-f.x, zz.y, fma(-f.y, zz.x, acc[c].y));
-      }
+    for (int b = 0; b < 4; ++b) {
+      const int c = ty + 16 * b;
+      acc[a][b] = (i >= n || c0 + c >= ncol) ? double2{0.0, 0.0}
+                  : (in_panel ? zs[i - j0][c] : Wk[i + (size_t)n * (c0 + c)]);
     }
+  }
+  for (int jp = 0; jp < w; ++jp) {
+    double2 f[4], z[4];
 #pragma unroll
-    for (int c = 0; c < GJ_CW; ++c)
-      if (c < nc) Wk[i + (size_t)n * (c0 + c)] = acc[c];
+    for (int a = 0; a < 4; ++a) f[a] = fs[tx + 16 * a][jp];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) z[b] = zs[jp][ty + 16 * b];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        acc[a][b].x = fma(-f[a].x, z[b].x, fma(f[a].y, z[b].y, acc[a][b].x));
+        acc[a][b].y = fma(-f[a].x, z[b].y, fma(-f[a].y, z[b].x, acc[a][b].y));
+      }
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int i = r0 + tx + 16 * a;
+    if (i >= n) continue;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int c = c0 + ty + 16 * b;
+      if (c < ncol) Wk[i + (size_t)n * c] = acc[a][b];
+    }
   }
 }
 

@@ -1353,8 +1353,9 @@ int obm_run(scocg_ctx& h, int K, int M, int L, const double2* g, const double2* 
     ev_phase.push_back(phase);
   };
   const int n = 2 * M, D = 2 * M + L, ncol = n + D;
-  DevBuf W, f, piv, fail, P, GR, U, Q, T, dos, lists;
+  DevBuf W, f, piv, Vj, fail, P, GR, U, Q, T, dos, lists;
   W.alloc(sizeof(double2) * (size_t)K * n * ncol);
+  Vj.alloc(sizeof(double2) * (size_t)K * obm::GJ_W * ncol);
   f.alloc(sizeof(double2) * (size_t)K * n * obm::GJ_W);
   piv.alloc(sizeof(double2) * (size_t)K * obm::GJ_W);
   fail.alloc(sizeof(int32_t) * K);
@@ -1426,14 +1427,18 @@ int obm_run(scocg_ctx& h, int K, int M, int L, const double2* g, const double2* 
     const int w = std::min(obm::GJ_W, n - j0);
     mark(1);
     hipLaunchKernelGGL(obm::k_gj_panel, dim3(K), dim3(obm::GJ_PNT), 0, st, Wp, f.as<double2>(),
-                       piv.as<double2>(), fail.as<int32_t>(), n, ncol, j0, w);
+                       piv.as<double2>(), Vj.as<double2>(), fail.as<int32_t>(), n, ncol, j0, w);
     KCHK();
     const int cols = ncol - j0 - w;  // > 0: the RHS columns always follow
     mark(1);
     mark(2);
-    hipLaunchKernelGGL(obm::k_gj_update, dim3(nblocks(cols, obm::GJ_CW), K), dim3(256), 0, st,
-                       Wp, f.as<double2>(), piv.as<double2>(), fail.as<int32_t>(), n, ncol, j0,
-                       w);
+    hipLaunchKernelGGL(obm::k_gj_sweep, dim3(nblocks(cols, 64), K), dim3(64), 0, st,
+                       Vj.as<double2>(), f.as<double2>(), piv.as<double2>(), fail.as<int32_t>(),
+                       n, ncol, j0, w);
+    KCHK();
+    hipLaunchKernelGGL(obm::k_gj_update, dim3(nblocks(cols, obm::GJ_T), nblocks(n, obm::GJ_T), K),
+                       dim3(256), 0, st, Wp, f.as<double2>(), Vj.as<double2>(),
+                       fail.as<int32_t>(), n, ncol, j0, w);
     KCHK();
     mark(2);
   }
