@@ -281,8 +281,8 @@ int scocg_apply_h(scocg_handle h, const void *x_dev, void *y_dev);
  *              2 panel updates of the other columns, 3 output rows, T and DOS.
  * Work runs on the handle's stream; the call returns after it completes.  The
  * handle's operator and last solve are not used or changed.  Device workspace of
- * about 16 K (2M (2M + D + 32) + 3 M^2 + 2 L M) bytes (plus K D^2 16 bytes when
- * gt_dev is NULL) is allocated for the call.
+ * about 16 K ((2M + 32) (2M + D) + 64 M + 3 M^2 + 2 L M) bytes (plus K D^2 16 bytes
+ * when gt_dev is NULL) is allocated for the call.
  * Returns SCOCG_BREAKDOWN (outputs of the affected energies NaN) if the 2M x 2M
  * system of an energy meets a zero pivot.
  */
