@@ -160,11 +160,12 @@ __global__ __launch_bounds__(256) void k_obm_init(const double2* __restrict__ g,
 // so each column is read and written once per panel instead of once per pivot.
 // A zero or non-finite pivot marks the energy failed; later kernels skip it.
 constexpr int GJ_W = 32;     // pivots per panel
-constexpr int GJ_PNT = 512;  // threads of the panel kernel
+// threads of the panel kernel: 512, or 1024 above n = 1024 rows (chosen at launch)
 
 // Vj [K][GJ_W][ncol]: row j0 + jj of every column right of the panel, as it stands
 // once its swap is done (its final row order); the update reads its sweep input
 // from here, so the tile that owns the panel rows can overwrite them in W.
+template <int GJ_PNT>
 __global__ __launch_bounds__(GJ_PNT) void k_gj_panel(double2* W, double2* F, double2* pivv,
                                                      double2* Vj, int32_t* fail, int n,
                                                      int ncol, int j0, int w) {

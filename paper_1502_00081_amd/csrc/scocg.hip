@@ -1426,8 +1426,12 @@ int obm_run(scocg_ctx& h, int K, int M, int L, const double2* g, const double2* 
   for (int j0 = 0; j0 < n; j0 += obm::GJ_W) {
     const int w = std::min(obm::GJ_W, n - j0);
     mark(1);
-    hipLaunchKernelGGL(obm::k_gj_panel, dim3(K), dim3(obm::GJ_PNT), 0, st, Wp, f.as<double2>(),
-                       piv.as<double2>(), Vj.as<double2>(), fail.as<int32_t>(), n, ncol, j0, w);
+    if (n <= 1024)  // each thread keeps at most two rows per pivot step
+      hipLaunchKernelGGL(obm::k_gj_panel<512>, dim3(K), dim3(512), 0, st, Wp, f.as<double2>(),
+                         piv.as<double2>(), Vj.as<double2>(), fail.as<int32_t>(), n, ncol, j0, w);
+    else
+      hipLaunchKernelGGL(obm::k_gj_panel<1024>, dim3(K), dim3(1024), 0, st, Wp, f.as<double2>(),
+                         piv.as<double2>(), Vj.as<double2>(), fail.as<int32_t>(), n, ncol, j0, w);
     KCHK();
     const int cols = ncol - j0 - w;  // > 0: the RHS columns always follow
     mark(1);
