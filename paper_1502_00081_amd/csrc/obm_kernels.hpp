@@ -152,19 +152,21 @@ __global__ __launch_bounds__(256) void k_obm_init(const double2* __restrict__ g,
 // the panel, keep the pivot value and the multipliers f^(j)_i = W(i, j)
 // (i != j; f^(j)_j = 0), and eliminate inside the panel columns only.
 //
-// Update kernel (columns right of the panel): with v_J the rows j0.. of a
-// column and F the panel's multipliers, the panel's w eliminations amount to
+// Columns right of the panel: with v_J the rows j0.. of a column and F the
+// panel's multipliers, the panel's w eliminations amount to
 //   z_j = (v_j - sum_{j' < j} f^(j')_j z_j') / pivot_j          (forward sweep)
 //   new v_j = z_j - sum_{j' > j} f^(j')_j z_j'                   (rows j of the panel)
 //   new v_i = v_i - sum_j' f^(j')_i z_j'                         (every other row)
-// so each column is read and written once per panel instead of once per pivot.
-// A zero or non-finite pivot marks the energy failed; later kernels skip it.
+// The panel kernel snapshots v_J (Vj) as each row settles, the sweep kernel turns
+// it into z in place, and the update kernel applies the last two lines by 64 x 64
+// tiles, so each element is read and written once per panel instead of once per
+// pivot.  A zero or non-finite pivot marks the energy failed; later kernels skip it.
 constexpr int GJ_W = 32;     // pivots per panel
 // threads of the panel kernel: 512, or 1024 above n = 1024 rows (chosen at launch)
 
 // Vj [K][GJ_W][ncol]: row j0 + jj of every column right of the panel, as it stands
-// once its swap is done (its final row order); the update reads its sweep input
-// from here, so the tile that owns the panel rows can overwrite them in W.
+// once its swap is done (its final row order); the sweep and update read it from
+// here, so the tile that owns the panel rows can overwrite them in W.
 template <int GJ_PNT>
 __global__ __launch_bounds__(GJ_PNT) void k_gj_panel(double2* W, double2* F, double2* pivv,
                                                      double2* Vj, int32_t* fail, int n,
