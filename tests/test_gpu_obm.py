@@ -123,6 +123,17 @@ def test_obm_wide_boundary_many_panels(dev):
     check_against_oracle(p, M, L, out, sl, sr, tol)
 
 
+def test_obm_single_energy_single_extra_row(dev):
+    """Degenerate sizes: one energy and one extra row (an interior grid point)."""
+    p, M, _ = wire(4, 4, 10, 1, extra=False)
+    extra = p.nx * p.ny * (p.nz // 2) + 5
+    p = p.with_(rhs_idx=np.concatenate([p.rhs_idx, [extra]]).astype(np.int64))
+    tol = 1e-11
+    out, sl, sr = gpu_obm(p, M, 1, dev, tol)
+    check_against_oracle(p, M, 1, out, sl, sr, tol)
+    assert out["dos"][0] > 0
+
+
 def test_obm_full_wire_workload(dev):
     """The benchmarked configuration (8x8x32, M = 256, L = 64, 16 energies) end to end."""
     p, M, L = W.obm_wire()
