@@ -70,11 +70,18 @@ enum { OR_CONVERGED = 0, OR_MAXITER = 1, OR_BREAKDOWN = 2 };
 static int64_t wrap(int64_t i, int64_t n) { return ((i % n) + n) % n; }
 
 /* y = H x.  Plain definition of the operator: a sum over the three axes of the
- * 1-D stencil, plus V x, plus the projector blocks. */
+ * 1-D stencil, plus V x, plus the projector blocks.  The periodic neighbour
+ * coordinates (i + k) mod n are tabulated once per call (wx, wy), so the loop does
+ * no integer division. */
 void oracle_apply_h(const oracle_op *op, const cplx *x, cplx *y)
 {
     const int64_t nx = op->nx, ny = op->ny, nz = op->nz;
     const int nf = op->nf;
+    /* wx[ix + nf + k] = (ix + k) mod nx for -nf <= k <= nf, likewise wy */
+    int64_t *wx = malloc(sizeof(int64_t) * (size_t)(nx + 2 * nf));
+    int64_t *wy = malloc(sizeof(int64_t) * (size_t)(ny + 2 * nf));
+    for (int64_t t = 0; t < nx + 2 * nf; ++t) wx[t] = wrap(t - nf, nx);
+    for (int64_t t = 0; t < ny + 2 * nf; ++t) wy[t] = wrap(t - nf, ny);
     for (int64_t iz = 0; iz < nz; ++iz)
         for (int64_t iy = 0; iy < ny; ++iy)
             for (int64_t ix = 0; ix < nx; ++ix) {
@@ -83,15 +90,17 @@ void oracle_apply_h(const oracle_op *op, const cplx *x, cplx *y)
                 for (int k = -nf; k <= nf; ++k) {
                     const int ak = k < 0 ? -k : k;
                     /* x axis, periodic */
-                    acc += op->coef[0 * (nf + 1) + ak] * x[wrap(ix + k, nx) + nx * (iy + ny * iz)];
+                    acc += op->coef[0 * (nf + 1) + ak] * x[wx[ix + nf + k] + nx * (iy + ny * iz)];
                     /* y axis, periodic */
-                    acc += op->coef[1 * (nf + 1) + ak] * x[ix + nx * (wrap(iy + k, ny) + ny * iz)];
+                    acc += op->coef[1 * (nf + 1) + ak] * x[ix + nx * (wy[iy + nf + k] + ny * iz)];
                     /* z axis, zero outside the transition region */
                     if (iz + k >= 0 && iz + k < nz)
                         acc += op->coef[2 * (nf + 1) + ak] * x[ix + nx * (iy + ny * (iz + k))];
                 }
                 y[i] = acc;
             }
+    free(wx);
+    free(wy);
     const int np = op->n_proj;
     for (int32_t a = 0; a < op->n_atoms; ++a) {
         cplx c[16];
