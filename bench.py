@@ -62,7 +62,9 @@ def parse():
     ap.add_argument("--no-symmetric", action="store_true",
                     help="obm_wire: keep every row of every column block (no mirroring)")
     ap.add_argument("--no-mixed", action="store_true",
-                    help="skip the mixed-vs-FP64 comparison on the 16x16x24 all-plane workload")
+                    help="skip the mixed-vs-FP64 comparison on a medium column subset")
+    ap.add_argument("--no-peapod", action="store_true",
+                    help="skip the peapod-shaped 64x64x160 sub-measurement")
     return ap.parse_args()
 
 
@@ -127,44 +129,64 @@ def cpu_baseline(p, n_energies, n_cols, iters_cap, tol, mean_iters):
                       f"per-pair counts)"}
 
 
-def mixed_vs_fp64(tol):
-    """Both precisions on the 16x16x24 workload with all 256 points of the iz=0 plane as
-    columns and 256 energies, full storage so every pair gets its FP64 true residual.
-    A solve counts when that true residual is <= 1.05 tol (the FP64 path stops on its
-    recursive estimate; 5 % covers the rounding gap).  The mixed path's time includes
-    its FP64 checks and refinement passes; the FP64 path's includes its check."""
+def mixed_vs_fp64(tol, energies=(64, 127), ncols=16):
+    """Both precisions where the Krylov vectors stream from HBM: the medium workload
+    (48x48x96, 40 atoms with projectors, eta = 1e-3) restricted to ncols columns (half on
+    each boundary plane) and the given energies (the middle and the top of the window),
+    full storage, so that every pair gets its FP64 true residual (the audit).  A solve
+    counts when that true residual is <= 1.05 tol (the FP64 path stops on its recursive
+    estimate; 5 % covers the rounding gap).  Three runs:
+      fp64:        complex128 vectors, FP64 check;
+      mixed_main:  complex64 vectors, FP64 check only (where the recurrence levels off);
+      mixed:       complex64 vectors, FP64 check and refinement passes.
+    Times include the checks and the refinement; the per-pair error of the mixed result
+    is taken against the FP64 result."""
     import torch
     from paper_1502_00081_amd import scocg, workload
-    p = workload.tiny_mixed()
+    base = workload.medium_fp64()
+    R0 = base.rhs_idx.size
+    cols = np.r_[base.rhs_idx[:ncols // 2], base.rhs_idx[R0 // 2:R0 // 2 + ncols // 2]]
+    p = base.with_(z=base.z[list(energies)], rhs_idx=cols)
     K, R, N = p.z.size, p.rhs_idx.size, p.n
     res, G = {}, {}
-    for name, prec, refine in (("fp64", scocg.FP64, 0), ("mixed", scocg.MIXED, 3)):
+    for name, prec, refine in (("fp64", scocg.FP64, 0), ("mixed_main", scocg.MIXED, 0),
+                               ("mixed", scocg.MIXED, 3)):
         h = scocg.create_from_problem(p, precision=prec, stream=torch.cuda.current_stream())
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        rc, rep = h.solve(p.z, p.rhs_idx, tol=tol, full=True, refine=refine, use_graph=True)
-        G[name] = torch.empty((K, R, N), dtype=torch.complex128, device="cuda")
-        h.green_columns(G[name])
+        rc, rep = h.solve(p.z, p.rhs_idx, tol=tol, full=True, refine=refine, use_graph=True,
+                          max_iter=200000)
+        if name != "mixed_main":
+            G[name] = torch.empty((K, R, N), dtype=torch.complex128, device="cuda")
+            h.green_columns(G[name])
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         h.destroy()
         tr = rep["true_resid"]
         ok = int((tr <= 1.05 * tol).sum())
         res[name] = {"solves_per_s": ok / wall, "solves": ok, "pairs": K * R,
-                     "wall_ms": wall * 1e3, "solve_ms_device": rep["solve_ms"],
-                     "seed_iters": int(rep["seed_iters"]), "refined_pairs": int(rep["refined"]),
-                     "true_resid_max": float(tr.max()), "true_resid_median": float(np.median(tr))}
+                     "pass_rate": ok / (K * R), "wall_ms": wall * 1e3,
+                     "solve_ms_device": rep["solve_ms"], "seed_iters": int(rep["seed_iters"]),
+                     "refined_pairs": int(rep["refined"]), "true_resid_max": float(tr.max()),
+                     "true_resid_median": float(np.median(tr))}
         say(f"mixed-vs-fp64 {name}: {ok}/{K * R} pairs <= tol in {wall * 1e3:.0f} ms "
-            f"({rep['seed_iters']} seed iterations, {rep['refined']} refined)")
+            f"({rep['seed_iters']} seed iterations, {rep['refined']} refined, true residual "
+            f"median {np.median(tr):.2e})")
     ref = G["fp64"]
     err = (torch.linalg.vector_norm(G["mixed"] - ref, dim=2) /
            torch.linalg.vector_norm(ref, dim=2)).cpu().numpy()
     del G, ref
     res["mixed"]["rel_err_vs_fp64_max"] = float(err.max())
     res["mixed"]["rel_err_vs_fp64_median"] = float(np.median(err))
+    res["mixed"]["rel_err_vs_fp64_per_pair"] = [[float(x) for x in row] for row in err]
     res["mixed_over_fp64"] = res["mixed"]["solves_per_s"] / res["fp64"]["solves_per_s"]
-    res["workload"] = {"name": p.name, "grid": [p.nx, p.ny, p.nz], "energies": K, "rhs": R,
-                       "storage": "full", "tol": tol}
+    res["cost_split_mixed_ms"] = {
+        "main_solve_and_check": res["mixed_main"]["wall_ms"],
+        "refinement": res["mixed"]["wall_ms"] - res["mixed_main"]["wall_ms"],
+        "fp64_solve_for_comparison": res["fp64"]["wall_ms"]}
+    res["workload"] = {"name": p.name, "grid": [p.nx, p.ny, p.nz], "energy_indices":
+                       list(map(int, energies)), "energies": K, "rhs": R, "storage": "full",
+                       "tol": tol}
     return res
 
 
@@ -315,11 +337,14 @@ def obm_measure(a, steps, warmup, wide=False):
     ts, to = float(np.mean(solve_s)), float(np.mean(obm_s))
     ph = np.mean(phases, axis=0)
     ncol = n + D
-    # panel updates (dominant arithmetic of the matching): for every panel of w pivots,
-    # each column right of it gets a rank-w update of all n rows (8 w flops per element,
-    # one complex FMA per pivot) and is read and written once (32 bytes per element)
+    # panel updates (dominant arithmetic of the matching), timed together as phase 2:
+    # k_gj_sweep first sweeps the w panel rows of every column right of the panel with
+    # the panel's lower multipliers (w (w - 1) / 2 complex FMAs per column), then
+    # k_gj_update gives each of those columns a rank-w update of all n rows (one complex
+    # FMA per pivot and element); 8 flops per complex FMA.  Bytes: the update reads and
+    # writes each element once (32 bytes per element)
     panels = [(j0, min(32, n - j0)) for j0 in range(0, n, 32)]
-    upd_flops = K * sum(8 * w * n * (ncol - j0 - w) for j0, w in panels)
+    upd_flops = K * sum(8 * (w * n + w * (w - 1) // 2) * (ncol - j0 - w) for j0, w in panels)
     upd_bytes = K * sum(32 * n * (ncol - j0 - w) for j0, w in panels)
     cpu = None
     if not a.no_cpu_baseline and not wide:
@@ -334,7 +359,7 @@ def obm_measure(a, steps, warmup, wide=False):
         "solve_ms": ts * 1e3, "matching_ms": to * 1e3,
         "matching_phase_ms": {"setup_products": ph[0], "panels": ph[1], "panel_updates": ph[2],
                               "outputs_T_dos": ph[3]},
-        "roofline": {"kernel": "k_gj_update", "bound": "alu",
+        "roofline": {"kernel": "k_gj_sweep+k_gj_update", "bound": "alu",
                      "achieved": upd_flops / (ph[2] * 1e-3) / 1e12, "peak": 78.6,
                      "unit": "TFLOP/s", "frac": upd_flops / (ph[2] * 1e-3) / 1e12 / 78.6,
                      "traffic": None, "bytes_per_s": upd_bytes / (ph[2] * 1e-3) / 1e9},
@@ -346,9 +371,107 @@ def obm_run(a, wide=False):
     print(json.dumps(obm_measure(a, a.steps, a.warmup, wide)), flush=True)
 
 
+def _capped_rates(p, rep, iters, prec_fp64):
+    """Per-launch algorithmic bytes, average HIP-event duration, GB/s and fraction of
+    8 TB/s of the two stencil passes of a capped solve (S = the right-hand-side points)
+    in which no pair froze.
+      r_{n+1} pass: 3 N s_v per (column, iteration): read r_n, r_{n-1}, write r_{n+1};
+      mu pass: N s_v per (column, iteration) read, plus the x, p update of the previous
+        iteration it carries: per (energy, row, column) x read and written (2 x 16 B) and
+        p read and written (2 x 16 B FP64, 2 x 8 B complex64); the mu launch of the first
+        iteration carries none, the update of the last runs in a separate flush."""
+    sv = 16 if prec_fp64 else 8
+    sp = 16 if prec_fp64 else 8
+    K, R, N = p.z.size, p.rhs_idx.size, p.n
+    B, nb = rep["block_width"], rep["n_blocks"]
+    cols_it = rep["block_iters"] * B  # (column, iteration) units incl. padding columns
+    lu, lm = rep["kernel_launches"]["update"], rep["kernel_launches"]["mu"]
+    tu, tm = rep["kernel_ms"]["update"], rep["kernel_ms"]["mu"]
+    upd = cols_it * N * 3 * sv
+    mu = cols_it * N * sv
+    nS = R  # S = the right-hand-side points
+    xp = (iters - 1) * K * nS * nb * B * (32 + 2 * sp)
+    out = {}
+    for name, by, ms, n in (("r_next_pass", upd, tu, lu), ("mu_pass_with_xp_update", mu + xp, tm, lm)):
+        gbs = by / (ms * 1e-3) / 1e9
+        out[name] = {"bytes_per_launch": by / n, "avg_launch_us": ms * 1e3 / n, "gbs": gbs,
+                     "frac_of_8tbs": gbs / HBM_PEAK_GBPS}
+    out["mu_pass_with_xp_update"]["xp_bytes_per_launch"] = xp / max(n, 1)
+    out["mu_pass_with_xp_update"]["mu_bytes_per_launch"] = mu / max(n, 1)
+    return out
+
+
+def peapod_large_measure(a, capped_iters=256):
+    """The peapod-shaped configuration (64x64x160 grid, 400 atoms on a 12.85 bohr cylinder
+    plus 60 on a 6.614 bohr sphere, 4 projectors each; 512 energies in [-0.5, 0.5] Ha,
+    eta = 5e-4; 512 + 512 boundary columns) on one GPU.
+      capped (FP64 and complex64 vectors): the full configuration in projected storage
+        for `capped_iters` seed iterations with every launch bracketed by HIP events (a
+        full solve needs ~1e5 iterations, half an hour): time per iteration and the
+        algorithmic GB/s of both stencil passes;
+      converged: 8 energies evenly spread over the window x 8 columns (4 per boundary
+        plane), FP64, projected storage, driven to tol: converged solves/s."""
+    import torch
+    from paper_1502_00081_amd import scocg, workload
+    t0 = time.perf_counter()
+    p = workload.peapod_large()
+    say(f"peapod: generated N={p.n}, {p.n_atoms} atoms in {time.perf_counter() - t0:.1f} s")
+    K, R = p.z.size, p.rhs_idx.size
+    stream = torch.cuda.current_stream()
+    A = scocg.AUTO
+    res = {"workload": p.name, "grid": [p.nx, p.ny, p.nz], "h": p.h, "atoms": p.n_atoms,
+           "energies": K, "rhs": R, "rows": R, "eta": float(p.z.imag[0]), "tol": a.tol,
+           "storage": "projected (S = the right-hand-side points)"}
+    for name, prec in (("capped_fp64", scocg.FP64), ("capped_mixed", scocg.MIXED)):
+        h = scocg.create_from_problem(p, precision=prec, stream=stream)
+        rc, rep = h.solve(p.z, p.rhs_idx, tol=a.tol, max_iter=16, tile=A, zchunk=A,
+                          shift_chunk=A)
+        say(f"peapod {name}: tuned tile {rep['tile']} zchunk {rep['zchunk']} shift chunk "
+            f"{rep['shift_chunk']} in {rep['tune_ms']:.0f} ms")
+        rc, rep = h.solve(p.z, p.rhs_idx, tol=a.tol, max_iter=capped_iters, tile=A, zchunk=A,
+                          shift_chunk=A, timing=1)
+        h.destroy()
+        assert rc == scocg.NOT_ALL_CONVERGED and (rep["status"] == scocg.PAIR_MAXITER).all()
+        r = {"iterations": capped_iters, "ms_per_iteration": rep["solve_ms"] / capped_iters,
+             "kernel_us_per_iteration": {k: rep["kernel_ms"][k] * 1e3 / rep["kernel_launches"][k]
+                                         for k in scocg.KERNEL_FAMILIES
+                                         if rep["kernel_launches"][k]},
+             "launch_shape": {"tile": rep["tile"], "zchunk": rep["zchunk"],
+                              "shift_chunk": rep["shift_chunk"]}}
+        r.update(_capped_rates(p, rep, capped_iters, prec == scocg.FP64))
+        res[name] = r
+        say(f"peapod {name}: {r['ms_per_iteration']:.2f} ms/iteration; r_(n+1) pass "
+            f"{r['r_next_pass']['gbs']:.0f} GB/s, mu + x/p pass "
+            f"{r['mu_pass_with_xp_update']['gbs']:.0f} GB/s")
+    res["capped_mixed_over_fp64_per_iteration"] = (res["capped_fp64"]["ms_per_iteration"] /
+                                                   res["capped_mixed"]["ms_per_iteration"])
+    # converged FP64 subsample
+    cols = np.r_[p.rhs_idx[:4], p.rhs_idx[R // 2:R // 2 + 4]]
+    ks = np.linspace(0, K - 1, 8).round().astype(int)
+    q = p.with_(z=p.z[ks], rhs_idx=cols)
+    h = scocg.create_from_problem(q, precision=scocg.FP64, stream=stream)
+    h.solve(q.z, q.rhs_idx, tol=a.tol, max_iter=16, tile=A, zchunk=A, shift_chunk=A)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    rc, rep = h.solve(q.z, q.rhs_idx, tol=a.tol, max_iter=400000, use_graph=True, tile=A,
+                      zchunk=A, shift_chunk=A)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t1
+    h.destroy()
+    conv = int((rep["status"] == scocg.PAIR_CONVERGED).sum())
+    res["converged_subsample"] = {
+        "pairs": int(q.z.size * q.rhs_idx.size), "energy_indices": [int(k) for k in ks],
+        "converged": conv, "seconds": dt, "solves_per_s": conv / dt,
+        "seed_iters": int(rep["seed_iters"]), "ms_per_iteration": dt * 1e3 / rep["seed_iters"],
+        "precision": "fp64"}
+    say(f"peapod converged subsample: {conv}/64 pairs in {dt:.1f} s, "
+        f"{rep['seed_iters']} seed iterations")
+    return res
+
+
 def copy_bandwidth(nbytes=1 << 30, reps=5):
-    """Achievable HBM bandwidth on this GPU: a plain device-to-device copy of nbytes,
-    timed with HIP events over reps copies; bytes read + written per second (GB/s)."""
+    """A plain device-to-device copy of nbytes (torch), timed with HIP events over reps
+    copies; bytes read + written per second (GB/s)."""
     import torch
     src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
     dst = torch.empty_like(src)
@@ -363,6 +486,22 @@ def copy_bandwidth(nbytes=1 << 30, reps=5):
     ms = e0.elapsed_time(e1)
     del src, dst
     return 2.0 * nbytes * reps / (ms * 1e-3) / 1e9
+
+
+def stream_bandwidth(h, nbytes=3 << 30, reps=10):
+    """The library's own streaming probe (scocg_stream_probe) over three 1 GiB arrays:
+    GB/s of a copy, of the r_{n+1} pass's mix (two reads, one write) and of reads only,
+    each with nontemporal and with ordinary accesses."""
+    import torch
+    buf = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    out = {}
+    for mode, name in ((0, "copy"), (1, "read2_write1"), (2, "read_only")):
+        for nt in (True, False):
+            out[f"{name}_{'nontemporal' if nt else 'ordinary'}"] = h.stream_probe(
+                buf, nbytes, mode, nontemporal=nt, reps=reps)
+    del buf
+    return out
 
 
 def main():
@@ -486,21 +625,29 @@ def main():
         h.green_columns(out)
         torch.cuda.synchronize()
         line["ms_per_step_graph_replay"] = (time.perf_counter() - tg) * 1e3
-    h.destroy()
     del out
-    # achievable bandwidth of this GPU (plain copy), and the r_{n+1} pass against it; not
-    # in counter-calibration runs, whose one plain copy must stay the only large one
+    # achievable bandwidth of this GPU: torch's copy and the library's own streaming
+    # probe with the r_{n+1} pass's access mix; the pass against the best of the latter.
+    # Not in counter-calibration runs, whose one plain copy must stay the only large one
     if a.calibrate_copy_mib <= 0:
         bw = copy_bandwidth()
+        sb = stream_bandwidth(h)
+        best = max(sb["read2_write1_nontemporal"], sb["read2_write1_ordinary"])
         rf = line["roofline"]
         rf["achievable_copy_gbs"] = bw
-        rf["frac_of_achievable"] = rf["achieved"] / bw
+        rf["stream_probe_gbs"] = sb
+        rf["achievable_r2w1_gbs"] = best
+        rf["frac_of_achievable"] = rf["achieved"] / best
         if rf["hbm_gbs_from_counters"] is not None:
-            rf["counters_frac_of_achievable"] = rf["hbm_gbs_from_counters"] / bw
-        say(f"copy kernel: {bw:.0f} GB/s achievable; r_(n+1) pass {rf['achieved']:.0f} GB/s "
-            f"algorithmic = {rf['frac_of_achievable']:.1%} of it")
+            rf["counters_frac_of_achievable"] = rf["hbm_gbs_from_counters"] / best
+        say(f"streaming probe: {sb}; r_(n+1) pass {rf['achieved']:.0f} GB/s algorithmic = "
+            f"{rf['frac_of_achievable']:.1%} of the two-reads-one-write rate")
+    h.destroy()
     if not a.no_mixed:
         line["mixed_vs_fp64"] = mixed_vs_fp64(a.tol)
+    if not a.no_peapod and a.workload == "medium_fp64":
+        # the largest configuration, as sub-measurements (a full solve of it takes ~30 min)
+        line["peapod_large"] = peapod_large_measure(a)
     if not a.no_obm:
         # the open-boundary step on its own workload (8x8x32 wire, 16 energies), for the
         # record; the headline value above is the medium solve alone

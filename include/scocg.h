@@ -84,7 +84,9 @@ typedef struct {
  *             an index may not repeat within one atom.
  *   atom_P    [entries][n_proj] host, projector values (row per entry).
  *   atom_D    [n_atoms][n_proj] host, Ha, projector energies.
- *   precision SCOCG_FP64 or SCOCG_MIXED.
+ *   precision SCOCG_FP64 or SCOCG_MIXED.  With SCOCG_MIXED the projector contraction
+ *             C_a = P_a^T X runs on FP32 matrix cores (the environment variable
+ *             SCOCG_PROJ=valu at create time keeps it on the vector ALUs, for A/B checks).
  *   hip_stream hipStream_t to enqueue on (NULL: the handle creates and owns a
  *             non-blocking stream of default priority).
  *   out       receives the handle (freed by scocg_destroy).
@@ -143,7 +145,7 @@ typedef struct {
 
 /* Autotuning: any of tile, zchunk, shift_chunk = SCOCG_AUTO makes scocg_solve time
    short trial runs (16 seed iterations from the initial state of this very problem)
-   of each candidate launch shape -- the 4 tile shapes x up to 6 z-chunk lengths around
+   of each candidate launch shape -- the 4 tile shapes x up to 8 z-chunk lengths around
    the default, then 3 shift chunks -- before the solve proper, keep the fastest, and
    cache it in the handle for this (column blocks, energies, rows) shape; later solves
    of that shape reuse it.  Trials run outside the timed region (scocg_report.tune_ms
@@ -217,8 +219,11 @@ typedef struct {
  * one captured hipGraph.
  *   hs        [n] distinct handles on one device and one stream, same precision and nf.
  *   probs     [n] per-region problem (host arrays, copied during the call).
- *   opts      common options; init_seed must be -1; SCOCG_AUTO shapes fall back to
- *             the defaults (one launch shape serves the whole batch).
+ *   opts      common options; init_seed must be -1.  One tile shape and one shift
+ *             chunk serve the whole batch: SCOCG_AUTO for tile or shift_chunk times
+ *             16-iteration trials of the whole batch per candidate before the solve
+ *             (scocg_report.tune_ms, every call); each region keeps the z-chunk of its
+ *             own plan (zchunk = 0 or SCOCG_AUTO) or the explicit one.
  *   reps      [n] or NULL: per-region reports (solve_ms is the whole batch's device
  *             time; kernel_ms/kernel_launches are the shared launches).
  *   region_ms [n] or NULL: device ms from the start of the batch to the host poll at
@@ -240,6 +245,7 @@ int scocg_green_columns(scocg_handle h, void *dst, int32_t dtype, int32_t dst_is
 
 /* Apply y = H x for complex128 device vectors x, y of length N (checking aid). */
 int scocg_apply_h(scocg_handle h, const void *x_dev, void *y_dev);
+
 
 /*
  * Open-boundary matching (Sec. 3B, Eqs. 18-24) and transmission (Sec. 2B, Eq. 14).
@@ -289,6 +295,21 @@ int scocg_apply_h(scocg_handle h, const void *x_dev, void *y_dev);
 int scocg_obm(scocg_handle h, int32_t K, int32_t M, int32_t L, const void *g_dev,
               const void *sig_l_dev, const void *sig_r_dev, void *gt_dev, double *trans,
               double *dos, double *phase_ms);
+
+/*
+ * Streaming bandwidth probe (a measuring aid: the ceiling the memory-bound passes are
+ * compared with).  Runs the access mix of one pass without its arithmetic over three
+ * equal arrays carved from buf: mode 0 copies (one read, one write, like a plain copy),
+ * mode 1 adds two arrays into the third (two reads, one write: the r_{n+1} pass), mode
+ * 2 only reads (the mu pass).  16-byte vectors, nontemporal = 1 with nontemporal loads
+ * and stores (as the passes stream r_{n-1} and r_{n+1}).  buf: device memory of the
+ * handle's device, `bytes` long (>= 12 KiB; use well beyond the 256 MB last-level
+ * cache); its contents are overwritten.  After one warm launch, reps launches are
+ * timed with HIP events on the handle's stream; *gbs receives bytes read + written per
+ * second / 1e9.
+ */
+int scocg_stream_probe(scocg_handle h, int32_t mode, int32_t nontemporal, void *buf,
+                       int64_t bytes, int32_t reps, double *gbs);
 
 /* Release every device buffer of the handle.  NULL is ignored. */
 void scocg_destroy(scocg_handle h);

@@ -23,6 +23,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace scocg {
 
 constexpr int WG = 256;  // threads per workgroup for the streaming kernels
@@ -141,6 +143,7 @@ struct ProjArgs {
   int n_proj, n_atoms;
   gptr<cT> dc;                // out [nb][n_atoms][4][B]: D_l C_l
   gptr<double2> qa;           // out [nb][n_atoms][B]: sum_l C_l D_l C_l (null: not needed)
+  int mfma;                   // complex64 columns: contract on FP32 matrix cores
 };
 
 template <typename T>
@@ -182,6 +185,10 @@ struct StencilArgs {
   gptr<const T> pval;         // [E][4] projector values
   gptr<const cT> dc;          // [nb][n_atoms][4][B] D_a P_a^T r
   int n_atoms;
+  gptr<const cT> pcv;         // [nb][n_ent][B] P_a D_a P_a^T r per atom-major entry (null:
+                              // apply from dc inside the pass)
+  gptr<const int32_t> pent;   // [E] atom-major entry of each point-major entry
+  int n_ent;
   gptr<const ColState> cols;  // [nb*B]
   gptr<const int32_t> blk_active;  // [nb] (null: all active)
   gptr<double2> part0;        // [nb][nwg][B] mu or rho partials, nwg = nzc*ntx*nty
@@ -301,6 +308,121 @@ __device__ __forceinline__ void proj_contract(const typename cplx_of<T>::type* _
   }
 }
 
+// The same contraction for complex64 columns (B = 16, i.e. 32 real columns) on FP32
+// matrix cores.  v_mfma_f32_4x4x1_16b_f32 forms 16 independent 4x4 outer products per
+// wave: block b (lanes 4b..4b+3, q = lane % 4) multiplies the 4 channels of one entry,
+// A[q] = P[e][q], by 4 real columns of it, B[q] = X[e][4 (b % 8) + q], accumulating
+// into D[i][q] (register i of lane 4b + q = channel i, column 4 (b % 8) + q).  Blocks
+// 0-7 take entry e, blocks 8-15 entry e + 1, so one instruction covers two entries x 32
+// columns with no padded rows.  Waves split the atom's entries; the two entry halves
+// are added across lanes l and l + 32, then the waves in a fixed order through LDS.
+typedef float scocg_v4f __attribute__((ext_vector_type(4)));
+
+template <int NT>
+__device__ __forceinline__ void proj_contract_mfma(const float2* __restrict__ r, int64_t bstride,
+                                                   const ProjArgs<float>& pa, int at, int cb,
+                                                   char* smem) {
+  constexpr int B = 16, NW = NT / 64;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int blk = lane >> 2, q = lane & 3, half = blk >> 3, g = blk & 7;
+  const float* rb = reinterpret_cast<const float*>(r + (int64_t)cb * bstride);
+  const int e0 = pa.aptr[at], e1 = pa.aptr[at + 1];
+  scocg_v4f acc = {0.f, 0.f, 0.f, 0.f};
+  for (int e = e0 + 2 * w + half; e - half < e1; e += 2 * NW) {
+    float av = 0.f, bv = 0.f;
+    if (e < e1) {
+      av = pa.aval[(int64_t)e * 4 + q];
+      bv = rb[(int64_t)pa.aidx[e] * (2 * B) + 4 * g + q];
+    }
+    acc = __builtin_amdgcn_mfma_f32_4x4x1f32(av, bv, acc, 0, 0, 0);
+  }
+  // entry halves: lanes l and l + 32 hold the same (channel, column) set
+  float v[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) v[i] = acc[i] + __shfl_xor(acc[i], 32);
+  float* sh = reinterpret_cast<float*>(smem);  // [NW][4][32]
+  if (lane < 32) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) sh[(w * 4 + i) * 32 + 4 * g + q] = v[i];
+  }
+  __syncthreads();
+  float* cs = sh + NW * 4 * 32;  // [4][32]: C (channel, real column), waves summed in order
+  if (tid < 128) {
+    float t = 0.f;
+    for (int ww = 0; ww < NW; ++ww) t += sh[ww * 128 + tid];
+    cs[tid] = t;
+  }
+  __syncthreads();
+  if (tid < B) {
+    const int c = tid;
+    float2* o = pa.dc + ((int64_t)cb * pa.n_atoms + at) * 4 * B + c;
+    double2 qq = mk(0, 0);
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+      const float d = l < pa.n_proj ? pa.aD[at * 4 + l] : 0.f;
+      const float cr = cs[l * 32 + 2 * c], ci = cs[l * 32 + 2 * c + 1];
+      float2 vv;
+      vv.x = d * cr;
+      vv.y = d * ci;
+      o[l * B] = vv;
+      qq.x += (double)cr * vv.x - (double)ci * vv.y;
+      qq.y += (double)cr * vv.y + (double)ci * vv.x;
+    }
+    if (pa.qa) pa.qa[((int64_t)cb * pa.n_atoms + at) * B + c] = qq;
+  }
+}
+
+// The application P_a (D_a C_a) for complex64 columns on FP32 matrix cores, as
+// per-entry products pc[cb][e][c] = sum_l P[e][l] (D_l C_l)[c] over the atom-major
+// entries e of atom `at` (the operator pass then adds them at their points).
+// v_mfma_f32_16x16x4f32 multiplies 16 entries x 4 channels (A: lane l holds
+// P[e_0 + l % 16][l / 16]) by 4 channels x 16 real columns (B: lane l holds channel
+// l / 16, real column l % 16 of D C), giving 16 entries x 16 columns (lane l: entries
+// e_0 + 4 (l / 16) + v in register v, column l % 16); two instructions cover the 32
+// real columns of a block.  Waves take 16-entry tiles in turn.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_proj_apply_mfma(ProjArgs<float> pa, int n_ent,
+                                                        float2* __restrict__ pc) {
+  constexpr int B = 16, NW = NT / 64;
+  const int at = blockIdx.x, cb = blockIdx.y;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int col = lane & 15, kq = lane >> 4;
+  const float2* dca = pa.dc + ((int64_t)cb * pa.n_atoms + at) * 4 * B;
+  const float2 d0 = dca[kq * B + (col >> 1)], d1 = dca[kq * B + 8 + (col >> 1)];
+  const float b0 = (col & 1) ? d0.y : d0.x, b1 = (col & 1) ? d1.y : d1.x;
+  const int e0 = pa.aptr[at], e1 = pa.aptr[at + 1];
+  float* out = reinterpret_cast<float*>(pc + (int64_t)cb * n_ent * B);
+  for (int eb = e0 + 16 * w; eb < e1; eb += 16 * NW) {
+    const int e = eb + col;
+    const float av = e < e1 ? pa.aval[(int64_t)e * 4 + kq] : 0.f;
+    const scocg_v4f z = {0.f, 0.f, 0.f, 0.f};
+    const scocg_v4f r0 = __builtin_amdgcn_mfma_f32_16x16x4f32(av, b0, z, 0, 0, 0);
+    const scocg_v4f r1 = __builtin_amdgcn_mfma_f32_16x16x4f32(av, b1, z, 0, 0, 0);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = eb + 4 * kq + v;
+      if (row < e1) {
+        out[(int64_t)row * 2 * B + col] = r0[v];
+        out[(int64_t)row * 2 * B + 16 + col] = r1[v];
+      }
+    }
+  }
+}
+
+// the contraction on the path the handle chose (matrix cores for complex64 columns)
+template <typename T, int B, int NT>
+__device__ __forceinline__ void proj_contract_any(const typename cplx_of<T>::type* __restrict__ r,
+                                                  int64_t bstride, const ProjArgs<T>& pa, int at,
+                                                  int cb, char* smem) {
+  if constexpr (std::is_same<T, float>::value && B == 16) {
+    if (pa.mfma) {
+      proj_contract_mfma<NT>(r, bstride, pa, at, cb, smem);
+      return;
+    }
+  }
+  proj_contract<T, B, NT>(r, bstride, pa, at, cb, smem);
+}
+
 template <typename T, int B>
 __global__ __launch_bounds__(WG) void k_proj(const typename cplx_of<T>::type* __restrict__ r,
                                               int64_t bstride, ProjArgs<T> pa,
@@ -308,7 +430,7 @@ __global__ __launch_bounds__(WG) void k_proj(const typename cplx_of<T>::type* __
   __shared__ __align__(16) char smem[8 * WG * sizeof(T)];
   const int at = blockIdx.x, cb = blockIdx.y;
   if (blk_active && !blk_active[cb]) return;
-  proj_contract<T, B, WG>(r, bstride, pa, at, cb, smem);
+  proj_contract_any<T, B, WG>(r, bstride, pa, at, cb, smem);
 }
 
 // Stencil pass over one (x-y tile, z-chunk, column block).
@@ -605,14 +727,22 @@ struct StencilWG {
           hr = fmat(a.co.cy[k], yp.x + ym.x, hr);
           hi = fmat(a.co.cy[k], yp.y + ym.y, hi);
         }
-        for (int e = ce0[m]; e < ce1[m]; ++e) {
-          const cT* dca = a.dc + ((int64_t)cb * a.n_atoms + a.patom[e]) * 4 * B + c;
-          const T* pvv = a.pval + (int64_t)e * 4;
+        if (a.pcv) {  // uniform: the per-entry products were formed beforehand
+          for (int e = ce0[m]; e < ce1[m]; ++e) {
+            const cT v = a.pcv[((int64_t)cb * a.n_ent + a.pent[e]) * B + c];
+            hr += v.x;
+            hi += v.y;
+          }
+        } else {
+          for (int e = ce0[m]; e < ce1[m]; ++e) {
+            const cT* dca = a.dc + ((int64_t)cb * a.n_atoms + a.patom[e]) * 4 * B + c;
+            const T* pvv = a.pval + (int64_t)e * 4;
 #pragma unroll
-          for (int l = 0; l < 4; ++l) {
-            const cT d = dca[l * B];
-            hr = fmat(pvv[l], d.x, hr);
-            hi = fmat(pvv[l], d.y, hi);
+            for (int l = 0; l < 4; ++l) {
+              const cT d = dca[l * B];
+              hr = fmat(pvv[l], d.x, hr);
+              hi = fmat(pvv[l], d.y, hi);
+            }
           }
         }
         cT* op = reinterpret_cast<cT*>(iobase + (uint32_t)(ip + NF) * pstride + qoff[m]);
@@ -723,7 +853,8 @@ void k_stencil(const StencilArgs<T>* __restrict__ regs, const int32_t* __restric
       const int at = bid % na, cb = bid / na;
       if (a.blk_active && !a.blk_active[cb]) return;
       // plane-0 view of the padded vector
-      proj_contract<T, B, NT>(rsrc + (int64_t)NF * a.nxy * B, a.bstride, a.proj, at, cb, smem);
+      proj_contract_any<T, B, NT>(rsrc + (int64_t)NF * a.nxy * B, a.bstride, a.proj, at, cb,
+                                  smem);
       return;
     }
     bid -= a.nproj_wg;

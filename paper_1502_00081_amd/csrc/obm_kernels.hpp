@@ -411,17 +411,20 @@ __global__ __launch_bounds__(256) void k_gj_update(double2* W, const double2* __
 }
 
 // G_T rows: rows 0..n-1 from the solved system (W columns n..n+D-1), rows
-// n..D-1 start as the unperturbed rows (the extra-row update adds to them).
+// n..D-1 start as the unperturbed rows (the extra-row update adds to them).  An
+// energy whose elimination met a zero pivot gets NaN in every row, so the
+// extra-row update that follows (an addition to these rows) leaves NaN too.
 __global__ __launch_bounds__(256) void k_obm_out(const double2* __restrict__ W,
-                                                 const double2* __restrict__ g, double2* gt, int n,
-                                                 int D) {
+                                                 const double2* __restrict__ g, double2* gt,
+                                                 const int32_t* __restrict__ fail, int n, int D) {
   const int k = blockIdx.z;
   const int c = blockIdx.x;
+  const bool bad = fail[k] != 0;
   const double2* Wk = W + (size_t)k * n * (n + D) + (size_t)n * (n + c);
   const double2* gk = g + (size_t)k * D * D + (size_t)D * c;
   double2* out = gt + (size_t)k * D * D + (size_t)D * c;
   for (int i = blockIdx.y * 256 + threadIdx.x; i < D; i += gridDim.y * 256)
-    out[i] = i < n ? Wk[i] : gk[i];
+    out[i] = bad ? double2{NAN, NAN} : (i < n ? Wk[i] : gk[i]);
 }
 
 // Gamma = i (Sigma - Sigma^H) (Eq. 16), M x M per energy.

@@ -142,9 +142,11 @@ struct scocg_ctx {
   int nx = 0, ny = 0, nz = 0, nxy = 0, nf = 4, n_proj = 0;
   int64_t N = 0;
   int n_atoms = 0;
+  int proj_mfma = 0;  // complex64 columns: projector contraction on FP32 matrix cores
   std::vector<double> coef;  // [3][nf+1]
   // operator arrays on the device (T = double or float by precision)
-  DevBuf vloc, aptr, aidx, aval, aD, prow, patom, pval;
+  DevBuf vloc, aptr, aidx, aval, aD, prow, patom, pval, pent;
+  int64_t n_ent = 0;  // projector entries (sum over atoms)
   // FP64 copies for the true-residual pass (aliases of the above for SCOCG_FP64)
   DevBuf vloc64, aval64, aD64, pval64;
   // last solve
@@ -203,7 +205,7 @@ void upload_operator(scocg_ctx& h, const double* vloc, const int64_t* atom_ptr,
   for (int a = 0; a < h.n_atoms; ++a)
     for (int l = 0; l < np; ++l) ad[a * 4 + l] = (T)atom_D[a * np + l];
   // transpose to point-major CSR: entries of one point in atom order
-  std::vector<int32_t> pr(h.N + 1, 0), pa(E);
+  std::vector<int32_t> pr(h.N + 1, 0), pa(E), pe(E);
   std::vector<T> pv(E * 4);
   for (int64_t e = 0; e < E; ++e) pr[ai[e] + 1]++;
   for (int64_t i = 0; i < h.N; ++i) pr[i + 1] += pr[i];
@@ -212,8 +214,11 @@ void upload_operator(scocg_ctx& h, const double* vloc, const int64_t* atom_ptr,
     for (int64_t e = ap[a]; e < ap[a + 1]; ++e) {
       const int32_t slot = fill[ai[e]]++;
       pa[slot] = a;
+      pe[slot] = (int32_t)e;
       for (int l = 0; l < 4; ++l) pv[(int64_t)slot * 4 + l] = av[e * 4 + l];
     }
+  h.n_ent = E;
+  upload(h.pent, pe, s);
   upload(h.aptr, ap, s);
   upload(h.aidx, ai, s);
   upload(h.aval, av, s);
@@ -298,6 +303,7 @@ struct Solver {
       case 2: return {16, 4, 512};
       case 3: return {8, 8, 1024};
       case 4: return {8, 8, 512};
+      case 5: return {16, 16, 1024};
       default: return {16, 8, 1024};
     }
   }
@@ -438,20 +444,6 @@ struct Solver {
     KCHK();
   }
 
-  // a one-off single-region stencil pass (operator apply): uploads a one-entry table
-  template <int MODE>
-  void launch_stencil_once(const cT* r, cT* io, int nb, const StencilGrid& g, cT* dc) {
-    StencilArgs<T> a = stencil_args(MODE, g, nb, nullptr, nullptr, nullptr, nullptr, dc, nullptr);
-    a.r = to_g(r);
-    a.io = to_g(io);
-    DevBuf tab, off;
-    upload(tab, std::vector<StencilArgs<T>>{a}, h.stream);
-    upload(off, std::vector<int32_t>{0, stencil_wgs(a, g)}, h.stream);
-    launch_table<MODE>(h.stream, h.nf, g.variant, full_tiles(g.variant), tab.as<StencilArgs<T>>(),
-                       off.as<int32_t>(), 1, stencil_wgs(a, g), 0);
-    HIPCHK(hipStreamSynchronize(h.stream));  // tab, off are freed on return
-  }
-
   ProjArgs<T> proj_args(cT* dc, double2* qa) const {
     ProjArgs<T> pa{};
     pa.aptr = to_g(h.aptr.as<int32_t>());
@@ -462,6 +454,7 @@ struct Solver {
     pa.n_atoms = h.n_atoms;
     pa.dc = to_g(dc);
     pa.qa = to_g(qa);
+    pa.mfma = h.proj_mfma;
     return pa;
   }
 
@@ -681,9 +674,12 @@ struct Solver {
       for (int v : vs) {
         const StencilGrid g0 = plan(S.nb, v, want_zc ? 0 : o.zchunk);
         std::vector<int> zcs = {g0.zc};
+        // shorter chunks re-read more queue planes but keep the tiles of a chunk
+        // marching closer together (halo reads that hit L2); longer ones the reverse
         if (want_zc)
-          for (int zc : {g0.zc / 2, g0.zc * 4 / 3, g0.zc * 3 / 2, g0.zc * 2, g0.zc * 4})
-            if (zc >= 4 && zc <= h.nz) zcs.push_back(zc);
+          for (int zc : {g0.zc / 8, g0.zc / 4, g0.zc / 2, g0.zc * 4 / 3, g0.zc * 3 / 2,
+                         g0.zc * 2, g0.zc * 4})
+            if (zc >= 6 && zc <= h.nz) zcs.push_back(zc);
         std::sort(zcs.begin(), zcs.end());
         zcs.erase(std::unique(zcs.begin(), zcs.end()), zcs.end());
         for (int zc : zcs) {
@@ -1265,26 +1261,142 @@ int64_t Solver<T, B>::iterate(const scocg_solve_opts& o, double* kms, int64_t* k
   return bt.iterate(o, kms, kcount, nullptr, nullptr);
 }
 
+// ---- streaming bandwidth probe (scocg_stream_probe): the access mixes of the stencil
+// passes without their arithmetic.  Each thread moves U 16-byte vectors per step of a
+// grid-stride loop over n vectors; loads of one step are issued before its stores.
+//   NR = 1: c = a            (a copy: one read, one write)
+//   NR = 2: c = a + b        (the r_{n+1} pass: two reads, one write)
+//   NR = 0: s += a           (the mu pass: reads only; one value per workgroup written)
+template <int NR, bool NT, int U>
+__global__ __launch_bounds__(256) void k_stream(const double2* __restrict__ a,
+                                                const double2* __restrict__ b,
+                                                double2* __restrict__ c, int64_t n,
+                                                double* __restrict__ sink) {
+  const int64_t stride = (int64_t)gridDim.x * 256 * U;
+  double2 acc = mk(0, 0);
+  for (int64_t i0 = (int64_t)blockIdx.x * 256 * U + threadIdx.x; i0 < n; i0 += stride) {
+    double2 va[U], vb[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = i0 + (int64_t)u * 256;
+      if (i < n) {
+        va[u] = NT ? ld_stream(a + i) : a[i];
+        if (NR == 2) vb[u] = NT ? ld_stream(b + i) : b[i];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = i0 + (int64_t)u * 256;
+      if (i >= n) continue;
+      if (NR == 0) {
+        acc = cadd(acc, va[u]);
+      } else {
+        const double2 v = NR == 2 ? cadd(va[u], vb[u]) : va[u];
+        if (NT) st_stream(c + i, v);
+        else c[i] = v;
+      }
+    }
+  }
+  if (NR == 0) {
+    __shared__ double sh[256];
+    sh[threadIdx.x] = acc.x + acc.y;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+      if (threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) sink[blockIdx.x] = sh[0];
+  }
+}
+
+// ---- operator apply y = H x (scocg_apply_h and its allocation-free variant)
+
+// one-entry argument table of a stencil launch (and its workgroup offsets {0, grid}),
+// written on the stream instead of copied from the host
+template <typename T>
+__global__ void k_put_table(StencilArgs<T> a, StencilArgs<T>* __restrict__ tab,
+                            int32_t* __restrict__ off, int grid) {
+  if (threadIdx.x == 0) {
+    *tab = a;
+    off[0] = 0;
+    off[1] = grid;
+  }
+}
+
+
+// Device workspace of one apply: x scattered into column 0 of a padded column block,
+// the stencil output block, the projector coefficients D_a P_a^T x, and the one-entry
+// argument table of the stencil launch (written by a kernel, not uploaded).  Offsets
+// are 256-byte aligned inside one region of apply_ws_bytes() bytes.
 template <typename T, int B>
-void apply_h_impl(scocg_ctx& h, const void* x, void* y) {
+struct ApplyWs {
   using cT = typename cplx_of<T>::type;
-  scocg_ctx::Solve tmp;
+  size_t o_tab = 0, o_off = 0, o_dc = 0, o_pc = 0, o_blk = 0, o_out = 0, bytes = 0;
+  bool pc = false;  // per-entry projector products (the matrix-core application)
+  explicit ApplyWs(const scocg_ctx& h) {
+    auto up = [](size_t v) { return (v + 255) / 256 * 256; };
+    const size_t blk = (((size_t)h.nz + 2 * h.nf) * h.nxy * B) * sizeof(cT);
+    pc = std::is_same<T, float>::value && h.proj_mfma && h.n_atoms > 0;
+    o_tab = 0;
+    o_off = up(sizeof(StencilArgs<T>));
+    o_dc = o_off + 256;
+    o_pc = o_dc + up((size_t)std::max(h.n_atoms, 1) * 4 * B * sizeof(cT));
+    o_blk = o_pc + (pc ? up((size_t)h.n_ent * B * sizeof(cT)) : 0);
+    o_out = o_blk + up(blk);
+    bytes = o_out + up(blk);
+  }
+};
+
+template <typename T, int B>
+void apply_h_run(scocg_ctx& h, const void* x, void* y, char* ws) {
+  using cT = typename cplx_of<T>::type;
+  const ApplyWs<T, B> L(h);
+  auto* tab = reinterpret_cast<StencilArgs<T>*>(ws + L.o_tab);
+  auto* off = reinterpret_cast<int32_t*>(ws + L.o_off);
+  cT* dc = reinterpret_cast<cT*>(ws + L.o_dc);
+  cT* blk = reinterpret_cast<cT*>(ws + L.o_blk);
+  cT* out = reinterpret_cast<cT*>(ws + L.o_out);
+  scocg_ctx::Solve tmp;  // no buffers: the solver object only plans and fills arguments
   Solver<T, B> sv(h, tmp);
-  DevBuf blk, out, dc;
-  blk.alloc((size_t)sv.bstride() * sizeof(cT));
-  out.alloc((size_t)sv.bstride() * sizeof(cT));
-  dc.alloc((size_t)std::max(h.n_atoms, 1) * 4 * B * sizeof(cT));
+  // every element of blk (padding planes and columns 1.. zero), of dc and of the
+  // interior planes of out that the gather reads is written below: nothing needs clearing
   hipLaunchKernelGGL((k_scatter_col0<T, B>), dim3(nblocks(sv.bstride(), WG)), dim3(WG), 0,
-                     h.stream, static_cast<const double2*>(x), blk.as<cT>(), sv.bstride(), h.N,
+                     h.stream, static_cast<const double2*>(x), blk, sv.bstride(), h.N,
                      sv.pad_points());
   KCHK();
-  sv.launch_proj(blk.as<cT>(), 1, dc.as<cT>(), nullptr);
+  sv.launch_proj(blk, 1, dc, nullptr);
   const auto g = sv.plan(1, 0, 0);
-  sv.template launch_stencil_once<MODE_APPLY>(blk.as<cT>(), out.as<cT>(), 1, g, dc.as<cT>());
-  hipLaunchKernelGGL((k_gather_col0<T, B>), dim3(nblocks(h.N, WG)), dim3(WG), 0, h.stream,
-                     out.as<cT>(), static_cast<double2*>(y), h.N, sv.pad_points());
+  StencilArgs<T> a = sv.stencil_args(MODE_APPLY, g, 1, nullptr, nullptr, nullptr, nullptr, dc,
+                                     nullptr);
+  a.r = to_g(static_cast<const cT*>(blk));
+  a.io = to_g(out);
+  if constexpr (std::is_same<T, float>::value) {
+    if (L.pc) {  // complex64: the application P_a (D_a C_a) on matrix cores as well
+      float2* pc = reinterpret_cast<float2*>(ws + L.o_pc);
+      hipLaunchKernelGGL((k_proj_apply_mfma<WG>), dim3(h.n_atoms, 1), dim3(WG), 0, h.stream,
+                         sv.proj_args(dc, nullptr), (int)h.n_ent, pc);
+      KCHK();
+      a.pcv = to_g(static_cast<const float2*>(pc));
+      a.pent = to_g(h.pent.as<int32_t>());
+      a.n_ent = (int)h.n_ent;
+    }
+  }
+  const int grid = Solver<T, B>::stencil_wgs(a, g);
+  hipLaunchKernelGGL((k_put_table<T>), dim3(1), dim3(1), 0, h.stream, a, tab, off, grid);
+  KCHK();
+  Solver<T, B>::template launch_table<MODE_APPLY>(h.stream, h.nf, g.variant,
+                                                  sv.full_tiles(g.variant), tab, off, 1, grid, 0);
+  hipLaunchKernelGGL((k_gather_col0<T, B>), dim3(nblocks(h.N, WG)), dim3(WG), 0, h.stream, out,
+                     static_cast<double2*>(y), h.N, sv.pad_points());
   KCHK();
   HIPCHK(hipStreamSynchronize(h.stream));
+}
+
+template <typename T, int B>
+void apply_h_impl(scocg_ctx& h, const void* x, void* y) {
+  DevBuf ws;
+  ws.alloc(ApplyWs<T, B>(h).bytes);
+  apply_h_run<T, B>(h, x, y, ws.as<char>());
 }
 
 bool all_finite(const double* p, int64_t n) {
@@ -1448,8 +1560,8 @@ int obm_run(scocg_ctx& h, int K, int M, int L, const double2* g, const double2* 
   }
   // 3. output rows: boundary rows from X, extra rows G(l, :) + G(l, b) Sigma_b X
   mark(3);
-  hipLaunchKernelGGL(obm::k_obm_out, dim3(D, nblocks(D, 256), K), dim3(256), 0, st, Wp, g, gt, n,
-                     D);
+  hipLaunchKernelGGL(obm::k_obm_out, dim3(D, nblocks(D, 256), K), dim3(256), 0, st, Wp, g, gt,
+                     fail.as<int32_t>(), n, D);
   KCHK();
   if (L > 0) {
     gemm(o_p, 2 * K, false, L, M, M, D, M, L, one, zero, 1);
@@ -1538,10 +1650,78 @@ scocg_solve_opts check_opts(const scocg_solve_opts* opts) {
 
 // All regions: prepare, one shared iteration loop (one launch per kernel family per
 // iteration), then per region the FP64 checks / refinement and the report.
+// Autotuning of a batch: one tile shape and one shift chunk serve every region (they
+// select the kernel instances of the shared launches); each region keeps the z-chunk
+// its own plan gives for that tile (zchunk = SCOCG_AUTO), or the explicit one.  Each
+// candidate is timed as 16 iterations of the whole batch from its initial state; the
+// winner is kept in every region's state.  Returns the device ms of the trials.
+template <typename T, int B>
+double tune_batch(std::vector<Solver<T, B>*>& ptr, const scocg_solve_opts& o, bool want_tile,
+                  bool want_kch) {
+  constexpr int kIters = 16;
+  hipStream_t st = ptr[0]->h.stream;
+  scocg_solve_opts ot = o;
+  ot.max_iter = kIters;
+  ot.timing = 0;
+  ot.use_graph = 0;
+  ot.poll_every = kIters;
+  const int zc_fixed = o.zchunk > 0 ? o.zchunk : 0;
+  auto trial = [&]() {
+    for (auto* p : ptr)
+      p->init_unit(p->zk.template as<double2>(), p->seed0,
+                   p->conv ? p->zk.template as<double2>() : nullptr);
+    Event a, b;
+    HIPCHK(hipEventRecord(a, st));
+    double km[SCOCG_K_FAMILIES] = {0};
+    int64_t kc[SCOCG_K_FAMILIES] = {0};
+    Batch<T, B> bt(ptr, ot);
+    bt.iterate(ot, km, kc, nullptr, nullptr);
+    HIPCHK(hipEventRecord(b, st));
+    return elapsed_ms(a, b);
+  };
+  auto set_tile = [&](int v) {
+    for (auto* p : ptr) p->set_grid(p->plan(p->S.nb, v, zc_fixed));
+  };
+  Event t0, t1;
+  HIPCHK(hipEventRecord(t0, st));
+  if (want_tile && ptr[0]->h.nf == 4) {
+    double best = INFINITY;
+    int bv = ptr[0]->S.g.variant;
+    for (int v : {1, 2, 3, 4}) {
+      set_tile(v);
+      const double ms = trial();
+      if (trace_on()) fprintf(stderr, "[scocg] batch tune tile %d: %.3f ms\n", v, ms);
+      if (ms < best) {
+        best = ms;
+        bv = v;
+      }
+    }
+    set_tile(bv);
+  }
+  if (want_kch) {
+    double best = INFINITY;
+    int bk = ptr[0]->S.kch;
+    for (int kch : {1, 4, 16}) {
+      for (auto* p : ptr) p->S.kch = kch;
+      const double ms = trial();
+      if (trace_on()) fprintf(stderr, "[scocg] batch tune shift chunk %d: %.3f ms\n", kch, ms);
+      if (ms < best) {
+        best = ms;
+        bk = kch;
+      }
+    }
+    for (auto* p : ptr) p->S.kch = bk;
+  }
+  HIPCHK(hipEventRecord(t1, st));
+  return elapsed_ms(t0, t1);
+}
+
 template <typename T, int B>
 int run_batch(int n, const scocg_handle* hs, const scocg_problem* pr, scocg_solve_opts o,
               scocg_report* reps, double* region_ms) {
-  // one launch shape for all regions: autotuning is not offered here
+  // SCOCG_AUTO: one tile shape and shift chunk for the whole batch, tuned on the batch
+  // itself before the timed region; z-chunks stay per region (each region's plan)
+  const bool auto_tile = o.tile == SCOCG_AUTO, auto_kch = o.shift_chunk == SCOCG_AUTO;
   if (o.tile == SCOCG_AUTO) o.tile = 0;
   if (o.zchunk == SCOCG_AUTO) o.zchunk = 0;
   if (o.shift_chunk == SCOCG_AUTO) o.shift_chunk = 0;
@@ -1555,6 +1735,8 @@ int run_batch(int n, const scocg_handle* hs, const scocg_problem* pr, scocg_solv
     sv.back()->prepare(pr[i].K, pr[i].z, pr[i].R, pr[i].rhs_idx, pr[i].nS, pr[i].s_idx, oi);
     ptr.push_back(sv.back().get());
   }
+  double tune_ms = 0.0;
+  if (auto_tile || auto_kch) tune_ms = tune_batch<T, B>(ptr, o, auto_tile, auto_kch);
   hipStream_t st = hs[0]->stream;
   Event e0, e1;
   HIPCHK(hipEventRecord(e0, st));
@@ -1583,8 +1765,8 @@ int run_batch(int n, const scocg_handle* hs, const scocg_problem* pr, scocg_solv
   const float ms = elapsed_ms(e0, e1);
   int rc = SCOCG_OK;
   for (int i = 0; i < n; ++i) {
-    const int r = ptr[i]->report(o, tres[i], refined[i], ms, kms, kcount, 0.0, 0,
-                                 reps ? &reps[i] : nullptr);
+    const int r = ptr[i]->report(o, tres[i], refined[i], ms, kms, kcount, tune_ms,
+                                 tune_ms > 0.0, reps ? &reps[i] : nullptr);
     if (r == SCOCG_BREAKDOWN || (r == SCOCG_NOT_ALL_CONVERGED && rc == SCOCG_OK)) rc = r;
     if (region_ms) region_ms[i] = done_ms[i];
   }
@@ -1621,6 +1803,11 @@ int scocg_create(const scocg_grid* g, const double* coef, const double* vloc, in
     h->nf = g->nf;
     h->n_proj = g->n_proj;
     h->precision = precision;
+    // SCOCG_PROJ=valu keeps the complex64 contraction on the vector ALUs (A/B checks)
+    {
+      const char* pe = getenv("SCOCG_PROJ");
+      h->proj_mfma = precision == SCOCG_MIXED && !(pe && std::string(pe) == "valu");
+    }
     HIPCHK(hipGetDevice(&h->device));
     h->stream = static_cast<hipStream_t>(hip_stream);
     if (!h->stream) {  // a private stream, so that solves can be graph-captured
@@ -1754,6 +1941,46 @@ int scocg_apply_h(scocg_handle h, const void* x_dev, void* y_dev) {
       apply_h_impl<double, 8>(*h, x_dev, y_dev);
     else
       apply_h_impl<float, 16>(*h, x_dev, y_dev);
+    return SCOCG_OK;
+  });
+}
+
+int scocg_stream_probe(scocg_handle h, int32_t mode, int32_t nontemporal, void* buf,
+                       int64_t bytes, int32_t reps, double* gbs) {
+  return guarded([&]() -> int {
+    require(h != nullptr && buf != nullptr && gbs != nullptr, "NULL argument");
+    require(mode >= 0 && mode <= 2, "mode must be 0, 1 or 2");
+    require(reps >= 1 && bytes >= 3 * 4096, "need reps >= 1 and at least 12 KiB");
+    HIPCHK(hipSetDevice(h->device));
+    require_device_range(buf, (size_t)bytes, h->device, "buf");
+    // three equal arrays of n 16-byte vectors (a, b, c) plus one double per workgroup
+    constexpr int U = 4;
+    const int grid = 256 * 8;
+    const int64_t n = ((bytes - grid * 8) / 3) / 16;
+    require(n >= 256, "buffer too small");
+    double2* a = static_cast<double2*>(buf);
+    double2* b = a + n;
+    double2* c = b + n;
+    double* sink = reinterpret_cast<double*>(c + n);
+    auto launch = [&]() {
+#define SCOCG_STREAM(NR, NT)                                                                  \
+  hipLaunchKernelGGL((k_stream<NR, NT, U>), dim3(grid), dim3(256), 0, h->stream, a, b, c, n, \
+                     sink)
+      if (mode == 0) { if (nontemporal) SCOCG_STREAM(1, true); else SCOCG_STREAM(1, false); }
+      else if (mode == 1) { if (nontemporal) SCOCG_STREAM(2, true); else SCOCG_STREAM(2, false); }
+      else { if (nontemporal) SCOCG_STREAM(0, true); else SCOCG_STREAM(0, false); }
+#undef SCOCG_STREAM
+      KCHK();
+    };
+    HIPCHK(hipMemsetAsync(buf, 0, (size_t)bytes, h->stream));
+    launch();  // warm
+    Event e0, e1;
+    HIPCHK(hipEventRecord(e0, h->stream));
+    for (int r = 0; r < reps; ++r) launch();
+    HIPCHK(hipEventRecord(e1, h->stream));
+    const double ms = elapsed_ms(e0, e1);
+    const double moved = (double)n * 16 * (mode == 0 ? 2 : mode == 1 ? 3 : 1) * reps;
+    *gbs = moved / (ms * 1e-3) / 1e9;
     return SCOCG_OK;
   });
 }

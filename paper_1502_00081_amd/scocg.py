@@ -23,8 +23,8 @@ PAIR_CONVERGED, PAIR_MAXITER, PAIR_BREAKDOWN, PAIR_STALLED = 0, 1, 2, 4
 C128, C64 = 0, 1
 
 EXPORTS = ("scocg_create", "scocg_solve", "scocg_batch_solve", "scocg_green_columns",
-           "scocg_apply_h", "scocg_obm", "scocg_destroy", "scocg_last_error",
-           "scocg_struct_size")
+           "scocg_apply_h", "scocg_obm", "scocg_stream_probe",
+           "scocg_destroy", "scocg_last_error", "scocg_struct_size")
 AUTO = -1  # SCOCG_AUTO: autotuned launch shape
 
 
@@ -98,6 +98,8 @@ def load(path: str = LIB_PATH):
     lib.scocg_batch_solve.restype = C.c_int
     lib.scocg_obm.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, P, P, P, P, P, P, P]
     lib.scocg_obm.restype = C.c_int
+    lib.scocg_stream_probe.argtypes = [P, C.c_int32, C.c_int32, P, C.c_int64, C.c_int32, P]
+    lib.scocg_stream_probe.restype = C.c_int
     for which, mirror in enumerate((Grid, SolveOpts, Report, Problem)):
         if lib.scocg_struct_size(which) != C.sizeof(mirror):
             raise RuntimeError(f"{path}: {mirror.__name__} is {C.sizeof(mirror)} bytes here, "
@@ -227,6 +229,15 @@ class Handle:
                               None if phase_ms is None else phase_ms.ctypes.data)
         _check(rc)
         return rc, trans, dos
+
+    def stream_probe(self, buf_dev, nbytes, mode, nontemporal=True, reps=10):
+        """scocg_stream_probe on a device buffer of nbytes: GB/s of the pass-like access mix
+        (mode 0 copy, 1 two reads + one write, 2 reads only)."""
+        g = np.zeros(1)
+        _check(load().scocg_stream_probe(self._h, int(mode), int(bool(nontemporal)),
+                                         _dev_ptr(buf_dev), int(nbytes), int(reps),
+                                         g.ctypes.data))
+        return float(g[0])
 
     def destroy(self):
         if self._h:

@@ -225,3 +225,61 @@ def test_obm_without_output_buffer_and_repeat(dev):
         assert np.array_equal(T1, T2) and np.array_equal(d1, d2)
     finally:
         h.destroy()
+
+
+def test_obm_singular_energy_gives_nan_outputs(dev):
+    """An energy whose 2M x 2M system I - G_bb Sigma_b is exactly singular with finite
+    entries (G_bb = I and Sigma = I) is reported as SCOCG_BREAKDOWN with NaN in every
+    output of that energy -- boundary and extra rows of G_T, T and the DOS -- while the
+    other energy of the same call is finite, equals a call with that energy alone bit for
+    bit, and solves Eq. 18 (I - G_bb Sigma_b) G_T(b, :) = G(b, :) with the extra rows
+    G_T(l, :) = G(l, :) + G(l, b) Sigma_b G_T(b, :)."""
+    M, L = 24, 5
+    n, D = 2 * M, 2 * M + L
+    rng = np.random.default_rng(11)
+    g = np.zeros((2, D, D), np.complex128)  # matrix orientation g[k][r, c]
+    g[0] = 0.05 * (rng.standard_normal((D, D)) + 1j * rng.standard_normal((D, D)))
+    g[0][:n, :n] = np.eye(n)
+    g[1] = 0.05 * (rng.standard_normal((D, D)) + 1j * rng.standard_normal((D, D)))
+    sig = np.broadcast_to(np.eye(M, dtype=np.complex128), (2, M, M)).copy()
+    sig[1] = 0.5 * sig[1] + 0.02 * (rng.standard_normal((M, M)) + 1j * rng.standard_normal((M, M)))
+    sig_r = sig.copy()
+
+    def col_major(a):
+        return torch.from_numpy(np.ascontiguousarray(a.transpose(0, 2, 1))).to(dev)
+
+    h = scocg.create_from_problem(wire(4, 4, 10, 1, extra=False)[0], precision=scocg.FP64)
+    lib = scocg.load()
+    try:
+        gd, sl, sr = col_major(g), col_major(sig), col_major(sig_r)
+        gt = torch.full((2, D, D), 7.0, dtype=torch.complex128, device=dev)
+        torch.cuda.synchronize()
+        T = np.zeros(4)
+        dos = np.zeros(2)
+        ptr = scocg._dev_ptr
+        rc = lib.scocg_obm(h._h, 2, M, L, ptr(gd), ptr(sl), ptr(sr), ptr(gt), T.ctypes.data,
+                           dos.ctypes.data, None)
+        assert rc == scocg.BREAKDOWN, rc
+        assert "1 energies" in scocg.last_error()
+        out = gt.cpu().numpy()
+        assert np.isnan(out[0]).all()
+        assert np.isnan(T[:2]).all() and np.isnan(dos[0])
+        assert np.isfinite(out[1]).all() and np.isfinite(T[2:]).all() and np.isfinite(dos[1])
+        # energy 1 alone gives the same bits
+        gt1 = torch.empty((1, D, D), dtype=torch.complex128, device=dev)
+        T1, d1 = np.zeros(2), np.zeros(1)
+        rc1 = lib.scocg_obm(h._h, 1, M, L, ptr(gd[1:]), ptr(sl[1:]), ptr(sr[1:]), ptr(gt1),
+                            T1.ctypes.data, d1.ctypes.data, None)
+        assert rc1 == scocg.OK
+        assert np.array_equal(gt1.cpu().numpy()[0], out[1])
+        assert np.array_equal(T1, T[2:]) and np.array_equal(d1, dos[1:])
+        # Eq. 18 on the rows of both blocks, then the extra rows
+        G = g[1]
+        Sb = np.zeros((n, n), np.complex128)
+        Sb[:M, :M], Sb[M:, M:] = sig[1], sig_r[1]
+        X = np.linalg.solve(np.eye(n) - G[:n, :n] @ Sb, G[:n, :])
+        ref = np.vstack([X, G[n:, :] + G[n:, :n] @ Sb @ X])
+        got = out[1].T  # column-major buffer -> matrix orientation
+        assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max(), np.abs(got - ref).max()
+    finally:
+        h.destroy()

@@ -11,7 +11,6 @@ All calls go through the C ABI (paper_1502_00081_amd.scocg).  Tolerances:
 import os
 import sys
 import time
-from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 import pytest
@@ -67,20 +66,6 @@ def say(msg):
             f.write(line)
     sys.__stderr__.write(line)
     sys.__stderr__.flush()
-
-
-def oracle_pairs_logged(p, pairs, rows, tol, workers=16):
-    """One oracle call per pair on a thread pool (ctypes releases the GIL), with a
-    line per finished pair."""
-    def one(kj):
-        t0 = time.perf_counter()
-        g, it, st, _ = oracle.cocg_unit_columns(p, p.z, p.rhs_idx, rows, [kj], tol=tol)
-        say(f"oracle pair {kj}: {int(it[0])} iterations, {time.perf_counter() - t0:.1f} s")
-        return g[0], int(it[0]), int(st[0])
-    with ThreadPoolExecutor(max_workers=workers) as ex:
-        res = list(ex.map(one, pairs))
-    return (np.array([r[0] for r in res]), np.array([r[1] for r in res]),
-            np.array([r[2] for r in res]))
 
 
 def oracle_columns(p, tol, rows=None):
@@ -155,7 +140,10 @@ def test_tiny_fp64_matches_oracle_columns(tiny_full):
     assert (d <= bound).all()
     assert rel.max() <= 1e-7
     # the residual history is not monotone, so a rounding-level change moves the
-    # first crossing of the tolerance by a few percent of the count
+    # first crossing of the tolerance: the oracle's own shifted and conventional
+    # routines (same iterates, other rounding) differ by up to 37 of 504 iterations
+    # (7.3 %) on this workload (test_freeze_iteration_drift_between_shifted_and_
+    # conventional pins that scale on the CPU)
     assert (np.abs(gap) <= 0.1 * it10 + 5).all()
 
 
@@ -339,43 +327,6 @@ def test_invalid_solve_arguments(dev):
     h.destroy()
 
 
-# ------------------------------------------------------------------------ full-size medium workload
-
-@pytest.mark.timeout(600)
-def test_medium_projected_sampled_pairs_vs_oracle(dev):
-    """48x48x96 grid, 40 atoms with projectors, 128 energies, 64 boundary RHS,
-    tol 1e-8 (the benchmarked launch): sampled pairs against the oracle, and
-    size-independent properties of G_S on every pair."""
-    p = W.medium_fp64()
-    h = scocg.create_from_problem(p, precision=scocg.FP64)
-    say(f"medium: created handle, N={p.n}, K={p.z.size}, R={p.rhs_idx.size}")
-    t0 = time.perf_counter()
-    rc, rep = h.solve(p.z, p.rhs_idx, tol=1e-8, use_graph=True, max_iter=20000)
-    say(f"medium: GPU solve rc={rc} in {time.perf_counter() - t0:.2f} s, "
-        f"{rep['seed_iters']} seed iterations, device {rep['solve_ms']:.1f} ms")
-    assert rc == scocg.OK and (rep["status"] == scocg.PAIR_CONVERGED).all()
-    G = h.green_columns()  # [K, R, R]
-    h.destroy()
-    eta = p.z.imag.min()
-    for k in range(0, p.z.size, 9):
-        g = G[k].T
-        assert np.abs(g - g.T).max() <= 1e-5 * np.abs(g).max()
-        assert (np.diag(g).imag < 0).all()
-    assert np.abs(G).max() <= 1.0 / eta
-    # sampled pairs: both boundary planes, energies up to where the oracle needs
-    # a few thousand iterations (the top of the window needs ~16000: minutes of CPU)
-    pairs = [(0, 0), (16, 63), (32, 5), (48, 50), (64, 17), (72, 40)]
-    ref, it, st = oracle_pairs_logged(p, pairs, p.rhs_idx, tol=1e-9)
-    assert (st == oracle.CONVERGED).all()
-    for s, (k, j) in enumerate(pairs):
-        d = np.linalg.norm(G[k, j] - ref[s])
-        say(f"pair {(k, j)}: |d| {d:.3e} rel {d / np.linalg.norm(ref[s]):.3e} "
-            f"iters gpu {rep['iters'][k, j]} oracle(1e-9) {it[s]}")
-        # a-priori bound (r_gpu + r_orc) / eta restricted to the rows S
-        assert d <= (1e-8 + 1e-9) / eta, (k, j, d)
-        assert d <= 1e-5 * np.linalg.norm(ref[s]), (k, j, d)
-
-
 # ------------------------------------------------------------------------ mixed precision (row a10)
 
 def test_fp64_true_residual_report_matches_oracle_operator(tiny_full, dev):
@@ -474,7 +425,7 @@ def test_peapod_shape_sampled_pairs_full_storage(dev):
     assert np.array_equal(rep["iters"], rep2["iters"])
     tr = true_residuals(p, G)
     say(f"true residual (oracle operator): max {tr.max():.3e}, median {np.median(tr):.3e}")
-    assert (tr <= 1.5 * tol).all(), tr.max()
+    assert (tr <= 1.1 * tol).all(), tr.max()
     eta = p.z.imag.min()
     for k in range(p.z.size):
         g = Gs[k].T  # g[i, j] = G(S_i, rhs_j)
@@ -576,21 +527,33 @@ def test_batched_uneven_regions_full_size_capped(dev):
 
 
 def test_conventional_sweep_matches_shifted_and_oracle(dev):
-    """The conventional sweep (every (energy, column) pair its own recurrence) reaches
-    the same Green's functions as the shifted solve within the resolvent bound, with
-    per-pair iteration counts close to the oracle's conventional COCG and to the
-    shifted solve's freeze iterations (equal in exact arithmetic)."""
+    """The conventional sweep (every (energy, column) pair its own recurrence, Sec. 3C)
+    reaches the oracle's columns element by element -- within the resolvent bound at
+    tol 1e-10 and within 1e-10 relative per column at tol 1e-12 -- and the shifted
+    solve's Green's functions, with per-pair iteration counts close to the oracle's
+    conventional COCG and to the shifted solve's freeze iterations (equal in exact
+    arithmetic)."""
     p = W.tiny_fp64()
     h = scocg.create_from_problem(p, precision=scocg.FP64)
     rc_s, rep_s = h.solve(p.z, p.rhs_idx, tol=1e-10, full=True)
     Gs = h.green_columns()
     rc_c, rep_c = h.solve(p.z, p.rhs_idx, tol=1e-10, full=True, conventional=True)
     Gc = h.green_columns()
+    rc_t, rep_t = h.solve(p.z, p.rhs_idx, tol=1e-12, full=True, conventional=True)
+    Gt = h.green_columns()
     h.destroy()
-    assert rc_s == scocg.OK and rc_c == scocg.OK
+    assert rc_s == scocg.OK and rc_c == scocg.OK and rc_t == scocg.OK
     assert (rep_c["status"] == scocg.PAIR_CONVERGED).all()
     assert (rep_c["true_resid"] <= 1.1e-10).all()
     eta = p.z.imag.min()
+    ref, _ = oracle_columns(p, tol=1e-13)
+    tr_c = true_residuals(p, Gc)
+    d_o = np.linalg.norm(Gc - ref, axis=2)
+    assert (d_o <= (tr_c + 1e-13) / eta).all(), (d_o / ((tr_c + 1e-13) / eta)).max()
+    rel_t = np.linalg.norm(Gt - ref, axis=2) / np.linalg.norm(ref, axis=2)
+    say(f"conventional vs oracle: tol 1e-10 max rel {(d_o / np.linalg.norm(ref, axis=2)).max():.2e}, "
+        f"tol 1e-12 max rel {rel_t.max():.2e}")
+    assert rel_t.max() <= 1e-10, rel_t.max()
     d = np.linalg.norm(Gc - Gs, axis=2)
     assert (d <= (rep_c["true_resid"] + rep_s["true_resid"]) / eta).all()
     it_c, it_s = rep_c["iters"], rep_s["iters"]
@@ -739,3 +702,57 @@ def test_symmetric_rows_in_a_batch_and_aux_seed_with_complex64(dev):
         assert (true_residuals(p, G) <= 1.5e-8).all()
     finally:
         h.destroy()
+
+
+@pytest.mark.parametrize("prec", [scocg.FP64, scocg.MIXED])
+def test_green_columns_complex64_output(dev, prec):
+    """SCOCG_C64 output (Eq. 17 columns as complex64): host and device copies equal the
+    complex128 output rounded to complex64, element for element, in projected and in
+    full storage and with mirrored (symmetric) rows."""
+    p = small(8, 8, 12, 4, True, K=5, nb=6, nt=5)
+    h = scocg.create_from_problem(p, precision=prec)
+    try:
+        for kw in (dict(), dict(full=True), dict(symmetric=True)):
+            rc, rep = h.solve(p.z, p.rhs_idx, tol=1e-10 if prec == scocg.FP64 else 1e-5, **kw)
+            G = h.green_columns()
+            G32 = h.green_columns(dtype=scocg.C64)
+            assert G32.dtype == np.complex64 and G32.shape == G.shape
+            assert np.array_equal(G32, G.astype(np.complex64)), kw
+            Gd = torch.empty(G.shape, dtype=torch.complex64, device=dev)
+            h.green_columns(out=Gd, dtype=scocg.C64)
+            assert np.array_equal(Gd.cpu().numpy(), G32), kw
+    finally:
+        h.destroy()
+
+
+def test_batch_autotuned_shape_equals_explicit_shape(dev):
+    """SCOCG_AUTO in a batch: one tile shape and shift chunk for all regions, tuned on the
+    batch itself (reported as tuned with its trial time); the result equals, bit for bit,
+    a batch run with that shape given explicitly, and matches the single solves within
+    the resolvent bound."""
+    regs = [small(16, 16, 10, 4, False, K=5, nb=2, nt=2, seed=3),
+            small(16, 16, 20, 4, True, K=9, nb=5, nt=4, seed=4)]
+    stream = torch.cuda.Stream()
+    hs = [scocg.create_from_problem(p, precision=scocg.FP64, stream=stream) for p in regs]
+    try:
+        A = scocg.AUTO
+        probs = [(p.z, p.rhs_idx) for p in regs]
+        rc, reps, _ = scocg.batch_solve(hs, probs, tol=1e-10, tile=A, zchunk=A, shift_chunk=A)
+        assert rc == scocg.OK
+        G1 = [h.green_columns() for h in hs]
+        t, k = reps[0]["tile"], reps[0]["shift_chunk"]
+        say(f"batch tuned: tile {t}, shift chunk {k}, zchunks {[r['zchunk'] for r in reps]}, "
+            f"{reps[0]['tune_ms']:.1f} ms of trials")
+        assert all(r["tuned"] and r["tune_ms"] > 0 for r in reps)
+        assert all(r["tile"] == t and r["shift_chunk"] == k for r in reps)
+        rc2, reps2, _ = scocg.batch_solve(hs, probs, tol=1e-10, tile=t, shift_chunk=k)
+        assert rc2 == scocg.OK and not reps2[0]["tuned"]
+        for h, G in zip(hs, G1):
+            assert np.array_equal(h.green_columns(), G)
+        eta = 1e-3
+        for h, p, G in zip(hs, regs, G1):
+            h.solve(p.z, p.rhs_idx, tol=1e-10)
+            assert np.abs(h.green_columns() - G).max() <= 4e-10 / eta
+    finally:
+        for h in hs:
+            h.destroy()
