@@ -149,13 +149,18 @@ def mixed_vs_fp64(tol, energies=(64, 127), ncols=16):
     p = base.with_(z=base.z[list(energies)], rhs_idx=cols)
     K, R, N = p.z.size, p.rhs_idx.size, p.n
     res, G = {}, {}
+    cap = 200000
     for name, prec, refine in (("fp64", scocg.FP64, 0), ("mixed_main", scocg.MIXED, 0),
                                ("mixed", scocg.MIXED, 3)):
         h = scocg.create_from_problem(p, precision=prec, stream=torch.cuda.current_stream())
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         rc, rep = h.solve(p.z, p.rhs_idx, tol=tol, full=True, refine=refine, use_graph=True,
-                          max_iter=200000)
+                          max_iter=cap)
+        if name == "fp64":
+            # the complex64 recurrence is capped at twice the FP64 seed iterations (it
+            # need not reach its floor here; the refinement passes take it from there)
+            cap = 2 * int(rep["seed_iters"])
         if name != "mixed_main":
             G[name] = torch.empty((K, R, N), dtype=torch.complex128, device="cuda")
             h.green_columns(G[name])
@@ -186,7 +191,7 @@ def mixed_vs_fp64(tol, energies=(64, 127), ncols=16):
         "fp64_solve_for_comparison": res["fp64"]["wall_ms"]}
     res["workload"] = {"name": p.name, "grid": [p.nx, p.ny, p.nz], "energy_indices":
                        list(map(int, energies)), "energies": K, "rhs": R, "storage": "full",
-                       "tol": tol}
+                       "tol": tol, "complex64_iteration_cap": cap}
     return res
 
 
@@ -200,23 +205,29 @@ def batched_regions_run(a):
     prec = scocg.FP64 if a.precision == "fp64" else scocg.MIXED
     stream = torch.cuda.Stream()
     hs = [scocg.create_from_problem(p, precision=prec, stream=stream) for p in regs]
-    kw = dict(tol=a.tol, use_graph=True, max_iter=a.max_iter if a.max_iter > 0 else 400000)
+    A = scocg.AUTO
+    # launch shapes tuned on the batch (one tile and shift chunk for all regions) and,
+    # for the region-by-region comparison, on each region alone
+    kw = dict(tol=a.tol, use_graph=True, max_iter=a.max_iter if a.max_iter > 0 else 400000,
+              tile=A, zchunk=A, shift_chunk=A)
     pairs = sum(p.z.size * p.rhs_idx.size for p in regs)
     say(f"batched regions: {len(regs)} regions, {pairs} pairs, precision {a.precision}")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     rc, reps, region_ms = scocg.batch_solve(hs, [(p.z, p.rhs_idx) for p in regs], **kw)
     torch.cuda.synchronize()
-    tb = time.perf_counter() - t0
+    # wall time of the solve proper: the autotuning trials (reported apart) excluded
+    tb = time.perf_counter() - t0 - reps[0]["tune_ms"] * 1e-3
     conv = sum(int((r["status"] == scocg.PAIR_CONVERGED).sum()) for r in reps)
-    say(f"batched: rc={rc}, {conv}/{pairs} converged in {tb:.1f} s")
+    say(f"batched: rc={rc}, {conv}/{pairs} converged in {tb:.1f} s (tile {reps[0]['tile']}, "
+        f"shift chunk {reps[0]['shift_chunk']}, {reps[0]['tune_ms']:.0f} ms of trials)")
     ts, conv_s = 0.0, 0
     if not a.no_sequential:
         for i, (h, p) in enumerate(zip(hs, regs)):
             t1 = time.perf_counter()
             rc1, rep1 = h.solve(p.z, p.rhs_idx, **kw)
             torch.cuda.synchronize()
-            ts += time.perf_counter() - t1
+            ts += time.perf_counter() - t1 - rep1["tune_ms"] * 1e-3
             conv_s += int((rep1["status"] == scocg.PAIR_CONVERGED).sum())
             say(f"region {i} alone: {rep1['seed_iters']} iterations, {time.perf_counter() - t1:.1f} s")
     for h in hs:
@@ -232,7 +243,10 @@ def batched_regions_run(a):
             "region_completion_ms": {"p50": float(np.percentile(region_ms, 50)),
                                      "p99": float(np.percentile(region_ms, 99)),
                                      "all": [round(float(x), 1) for x in region_ms]},
-            "region_seed_iters": [int(r["seed_iters"]) for r in reps]}
+            "region_seed_iters": [int(r["seed_iters"]) for r in reps],
+            "launch_shape": {"tile": reps[0]["tile"], "shift_chunk": reps[0]["shift_chunk"],
+                             "zchunks": [int(r["zchunk"]) for r in reps],
+                             "tune_ms": reps[0]["tune_ms"]}}
     if not a.no_sequential:
         line["sequential"] = {"solves_per_s": conv_s / ts, "seconds": ts, "converged": conv_s}
     print(json.dumps(line), flush=True)
@@ -374,7 +388,7 @@ def obm_run(a, wide=False):
 def _capped_rates(p, rep, iters, prec_fp64):
     """Per-launch algorithmic bytes, average HIP-event duration, GB/s and fraction of
     8 TB/s of the two stencil passes of a capped solve (S = the right-hand-side points)
-    in which no pair froze.
+    of `iters` iterations.
       r_{n+1} pass: 3 N s_v per (column, iteration): read r_n, r_{n-1}, write r_{n+1};
       mu pass: N s_v per (column, iteration) read, plus the x, p update of the previous
         iteration it carries: per (energy, row, column) x read and written (2 x 16 B) and
@@ -383,14 +397,18 @@ def _capped_rates(p, rep, iters, prec_fp64):
     sv = 16 if prec_fp64 else 8
     sp = 16 if prec_fp64 else 8
     K, R, N = p.z.size, p.rhs_idx.size, p.n
-    B, nb = rep["block_width"], rep["n_blocks"]
+    B = rep["block_width"]
     cols_it = rep["block_iters"] * B  # (column, iteration) units incl. padding columns
     lu, lm = rep["kernel_launches"]["update"], rep["kernel_launches"]["mu"]
     tu, tm = rep["kernel_ms"]["update"], rep["kernel_ms"]["mu"]
     upd = cols_it * N * 3 * sv
     mu = cols_it * N * sv
     nS = R  # S = the right-hand-side points
-    xp = (iters - 1) * K * nS * nb * B * (32 + 2 * sp)
+    # pair (k, j) is updated in iterations 0 .. f-1 (f: its freeze iteration, the cap for
+    # pairs still running); the update of iteration n runs in the mu launch of n + 1, the
+    # last iteration's in the flush
+    upd_in_mu = np.minimum(rep["iters"], iters - 1).sum()
+    xp = int(upd_in_mu) * nS * (32 + 2 * sp)
     out = {}
     for name, by, ms, n in (("r_next_pass", upd, tu, lu), ("mu_pass_with_xp_update", mu + xp, tm, lm)):
         gbs = by / (ms * 1e-3) / 1e9
@@ -431,8 +449,9 @@ def peapod_large_measure(a, capped_iters=256):
         rc, rep = h.solve(p.z, p.rhs_idx, tol=a.tol, max_iter=capped_iters, tile=A, zchunk=A,
                           shift_chunk=A, timing=1)
         h.destroy()
-        assert rc == scocg.NOT_ALL_CONVERGED and (rep["status"] == scocg.PAIR_MAXITER).all()
-        r = {"iterations": capped_iters, "ms_per_iteration": rep["solve_ms"] / capped_iters,
+        assert rc in (scocg.OK, scocg.NOT_ALL_CONVERGED), rc
+        r = {"iterations": capped_iters,
+             "pairs_still_running": int((rep["status"] == scocg.PAIR_MAXITER).sum()), "ms_per_iteration": rep["solve_ms"] / capped_iters,
              "kernel_us_per_iteration": {k: rep["kernel_ms"][k] * 1e3 / rep["kernel_launches"][k]
                                          for k in scocg.KERNEL_FAMILIES
                                          if rep["kernel_launches"][k]},

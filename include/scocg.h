@@ -84,9 +84,11 @@ typedef struct {
  *             an index may not repeat within one atom.
  *   atom_P    [entries][n_proj] host, projector values (row per entry).
  *   atom_D    [n_atoms][n_proj] host, Ha, projector energies.
- *   precision SCOCG_FP64 or SCOCG_MIXED.  With SCOCG_MIXED the projector contraction
- *             C_a = P_a^T X runs on FP32 matrix cores (the environment variable
- *             SCOCG_PROJ=valu at create time keeps it on the vector ALUs, for A/B checks).
+ *   precision SCOCG_FP64 or SCOCG_MIXED.  With SCOCG_MIXED and the environment
+ *             variable SCOCG_PROJ=mfma at create time, the projector contraction
+ *             C_a = P_a^T X (in solves and scocg_apply_h) and the application
+ *             P_a (D_a C_a) (in scocg_apply_h) run on FP32 matrix cores; by default
+ *             both run on the vector ALUs, which is faster for 4 channels.
  *   hip_stream hipStream_t to enqueue on (NULL: the handle creates and owns a
  *             non-blocking stream of default priority).
  *   out       receives the handle (freed by scocg_destroy).

@@ -48,6 +48,27 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Element-wise loops over a long vector may run on several threads: every element is
+ * computed exactly as in the serial loop, so the results do not depend on the thread
+ * count.  Reductions (dot products and norms) always run serially, in index order.
+ * A top-level call uses every thread; inside the per-system loop of the batch routine,
+ * each system gets its share (g_inner, set per system thread). */
+static _Thread_local int g_inner = 1;
+
+static int par_n(int64_t n)
+{
+#ifdef _OPENMP
+    if (n < 65536) return 1;
+    return omp_in_parallel() ? g_inner : omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}
 
 typedef double complex cplx;
 
@@ -82,6 +103,9 @@ void oracle_apply_h(const oracle_op *op, const cplx *x, cplx *y)
     int64_t *wy = malloc(sizeof(int64_t) * (size_t)(ny + 2 * nf));
     for (int64_t t = 0; t < nx + 2 * nf; ++t) wx[t] = wrap(t - nf, nx);
     for (int64_t t = 0; t < ny + 2 * nf; ++t) wy[t] = wrap(t - nf, ny);
+    /* every y[i] of the stencil part depends on x only: planes are independent */
+#pragma omp parallel for schedule(static) num_threads(par_n(nx * ny * nz)) \
+    if (par_n(nx * ny * nz) > 1)
     for (int64_t iz = 0; iz < nz; ++iz)
         for (int64_t iy = 0; iy < ny; ++iy)
             for (int64_t ix = 0; ix < nx; ++ix) {
@@ -137,6 +161,7 @@ static void apply_a(const oracle_op *op, cplx z, const cplx *v, cplx *w)
 {
     const int64_t n = op_n(op);
     oracle_apply_h(op, v, w);
+#pragma omp parallel for schedule(static) num_threads(par_n(n)) if (par_n(n) > 1)
     for (int64_t i = 0; i < n; ++i) w[i] = z * v[i] - w[i];
 }
 
@@ -199,11 +224,14 @@ int oracle_cocg(const oracle_op *op, const cplx *zp, const cplx *b, double tol, 
         }
         const cplx alpha = rho / denom;                     /* alpha_{n-1} */
         const cplx c = beta_prev * alpha / alpha_prev;      /* beta_{n-2} alpha_{n-1} / alpha_{n-2} */
+#pragma omp parallel for schedule(static) num_threads(par_n(n)) if (par_n(n) > 1)
         for (int64_t i = 0; i < n; ++i) x[i] += alpha * p[i];
+#pragma omp parallel for schedule(static) num_threads(par_n(n)) if (par_n(n) > 1)
         for (int64_t i = 0; i < n; ++i)
             r_next[i] = (1.0 + c) * r[i] - alpha * ar[i] - c * r_prev[i];
         const cplx rho_next = bil(n, r_next, r_next);
         const cplx beta = rho_next / rho;                   /* beta_{n-1} */
+#pragma omp parallel for schedule(static) num_threads(par_n(n)) if (par_n(n) > 1)
         for (int64_t i = 0; i < n; ++i) p[i] = r_next[i] + beta * p[i];
         const double res = nrm2(n, r_next);
         if (hist_alpha_re) { hist_alpha_re[it - 1] = creal(alpha); hist_alpha_im[it - 1] = cimag(alpha); }
@@ -227,7 +255,9 @@ done:
  * Many independent systems (z_k, e_{j}) at once: system s uses z[sys_k[s]] and
  * b = e_{rhs[sys_j[s]]}; its solution restricted to rows[0..n_rows) goes to
  * out[s*n_rows ...]; status and iteration count per system.  OpenMP over
- * systems (when compiled with it); each system is the sequential routine above.
+ * systems (when compiled with it); with fewer systems than threads, each system's
+ * element-wise loops use the threads left over.  Either way each system's
+ * arithmetic is that of the sequential routine.
  */
 int oracle_cocg_unit_batch(const oracle_op *op, int64_t n_sys, const cplx *zs,
                            const int64_t *rhs, const int64_t *rows, int64_t n_rows,
@@ -236,8 +266,16 @@ int oracle_cocg_unit_batch(const oracle_op *op, int64_t n_sys, const cplx *zs,
 {
     const int64_t n = op_n(op);
     int bad = 0;
-#pragma omp parallel for schedule(dynamic, 1) reduction(| : bad)
+    int outer = 1, inner = 1;
+#ifdef _OPENMP
+    const int nt = omp_get_max_threads();
+    outer = n_sys < nt ? (int)(n_sys > 0 ? n_sys : 1) : nt;
+    inner = nt / outer;
+    if (inner > 1 && omp_get_max_active_levels() < 2) omp_set_max_active_levels(2);
+#endif
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : bad) num_threads(outer)
     for (int64_t s = 0; s < n_sys; ++s) {
+        g_inner = inner;
         cplx *b = calloc(n, sizeof(cplx));
         cplx *x = malloc(sizeof(cplx) * n);
         if (!b || !x) { bad |= 1; free(b); free(x); continue; }

@@ -328,13 +328,22 @@ __device__ __forceinline__ void proj_contract_mfma(const float2* __restrict__ r,
   const float* rb = reinterpret_cast<const float*>(r + (int64_t)cb * bstride);
   const int e0 = pa.aptr[at], e1 = pa.aptr[at + 1];
   scocg_v4f acc = {0.f, 0.f, 0.f, 0.f};
-  for (int e = e0 + 2 * w + half; e - half < e1; e += 2 * NW) {
-    float av = 0.f, bv = 0.f;
-    if (e < e1) {
-      av = pa.aval[(int64_t)e * 4 + q];
-      bv = rb[(int64_t)pa.aidx[e] * (2 * B) + 4 * g + q];
+  // U entry pairs per step: their gathers are all in flight before the first MFMA
+  constexpr int U = 4;
+  for (int eb = e0 + 2 * w; eb < e1; eb += 2 * NW * U) {
+    float av[U], bv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = eb + 2 * NW * u + half;
+      av[u] = 0.f;
+      bv[u] = 0.f;
+      if (e < e1) {
+        av[u] = pa.aval[(int64_t)e * 4 + q];
+        bv[u] = rb[(int64_t)pa.aidx[e] * (2 * B) + 4 * g + q];
+      }
     }
-    acc = __builtin_amdgcn_mfma_f32_4x4x1f32(av, bv, acc, 0, 0, 0);
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc = __builtin_amdgcn_mfma_f32_4x4x1f32(av[u], bv[u], acc, 0, 0, 0);
   }
   // entry halves: lanes l and l + 32 hold the same (channel, column) set
   float v[4];
@@ -409,7 +418,8 @@ __global__ __launch_bounds__(NT) void k_proj_apply_mfma(ProjArgs<float> pa, int 
   }
 }
 
-// the contraction on the path the handle chose (matrix cores for complex64 columns)
+// the contraction on the path the handle chose (matrix cores for complex64 columns on
+// request, else the vector ALUs)
 template <typename T, int B, int NT>
 __device__ __forceinline__ void proj_contract_any(const typename cplx_of<T>::type* __restrict__ r,
                                                   int64_t bstride, const ProjArgs<T>& pa, int at,

@@ -1803,10 +1803,12 @@ int scocg_create(const scocg_grid* g, const double* coef, const double* vloc, in
     h->nf = g->nf;
     h->n_proj = g->n_proj;
     h->precision = precision;
-    // SCOCG_PROJ=valu keeps the complex64 contraction on the vector ALUs (A/B checks)
+    // SCOCG_PROJ=mfma puts the complex64 projector contraction (and the application in
+    // scocg_apply_h) on FP32 matrix cores; the vector-ALU paths are the default (faster
+    // for this 4-channel contraction, measured)
     {
       const char* pe = getenv("SCOCG_PROJ");
-      h->proj_mfma = precision == SCOCG_MIXED && !(pe && std::string(pe) == "valu");
+      h->proj_mfma = precision == SCOCG_MIXED && pe && std::string(pe) == "mfma";
     }
     HIPCHK(hipGetDevice(&h->device));
     h->stream = static_cast<hipStream_t>(hip_stream);

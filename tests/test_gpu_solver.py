@@ -756,3 +756,42 @@ def test_batch_autotuned_shape_equals_explicit_shape(dev):
     finally:
         for h in hs:
             h.destroy()
+
+
+def test_projectors_on_matrix_cores_match_oracle(dev, monkeypatch):
+    """SCOCG_PROJ=mfma: the complex64 projector contraction (v_mfma_f32_4x4x1_16b) and
+    application (v_mfma_f32_16x16x4) agree with the oracle's operator within the FP32
+    rounding bound, and a complex64 solve with them certifies every pair by its FP64
+    true residual after refinement and matches the vector-ALU solve within the two
+    residuals' resolvent bound."""
+    monkeypatch.setenv("SCOCG_PROJ", "mfma")
+    for shape in ((8, 8, 12), (48, 48, 20), (4, 4, 3)):
+        p = small(*shape, 4, True, n_atoms=5)
+        h = scocg.create_from_problem(p, precision=scocg.MIXED)
+        try:
+            rng = np.random.default_rng(2)
+            v = rng.standard_normal(p.n) + 1j * rng.standard_normal(p.n)
+            x = torch.from_numpy(v).to(dev)
+            y = torch.empty_like(x)
+            h.apply_h(x, y)
+            ref = oracle.apply_h(p, v)
+            scale = oracle.apply_h(abs_problem(p), np.abs(v.real) + np.abs(v.imag) + 0j).real
+            err = np.abs(y.cpu().numpy() - ref)
+            assert (err <= 32 * U32 * scale + 1e-300).all(), float((err / scale).max())
+        finally:
+            h.destroy()
+    p = small(8, 8, 12, 4, True, K=4, n_atoms=5)
+    tol = 1e-8
+    out = {}
+    for mode in ("mfma", "valu"):
+        monkeypatch.setenv("SCOCG_PROJ", mode)
+        h = scocg.create_from_problem(p, precision=scocg.MIXED)
+        try:
+            rc, rep = h.solve(p.z, p.rhs_idx, tol=tol, full=True, refine=3)
+            assert rc == scocg.OK and (rep["true_resid"] <= tol).all(), mode
+            out[mode] = (h.green_columns(), rep["true_resid"])
+        finally:
+            h.destroy()
+    eta = p.z.imag.min()
+    d = np.linalg.norm(out["mfma"][0] - out["valu"][0], axis=2)
+    assert (d <= (out["mfma"][1] + out["valu"][1]) / eta).all()
