@@ -54,7 +54,8 @@ def parse():
     ap.add_argument("--fixed-shape", action="store_true",
                     help="default launch shape instead of the autotuned one")
     ap.add_argument("--shape", default="",
-                    help="explicit launch shape 'tile,zchunk,shift_chunk' (no autotuning)")
+                    help="explicit launch shape 'tile,zchunk,shift_chunk[,cache_mode]' (no "
+                         "autotuning)")
     ap.add_argument("--no-sequential", action="store_true",
                     help="batched_regions: skip the region-by-region comparison")
     ap.add_argument("--no-obm", action="store_true",
@@ -209,7 +210,7 @@ def batched_regions_run(a):
     # launch shapes tuned on the batch (one tile and shift chunk for all regions) and,
     # for the region-by-region comparison, on each region alone
     kw = dict(tol=a.tol, use_graph=True, max_iter=a.max_iter if a.max_iter > 0 else 400000,
-              tile=A, zchunk=A, shift_chunk=A)
+              tile=A, zchunk=A, shift_chunk=A, cache_mode=A)
     pairs = sum(p.z.size * p.rhs_idx.size for p in regs)
     say(f"batched regions: {len(regs)} regions, {pairs} pairs, precision {a.precision}")
     torch.cuda.synchronize()
@@ -443,11 +444,11 @@ def peapod_large_measure(a, capped_iters=256):
     for name, prec in (("capped_fp64", scocg.FP64), ("capped_mixed", scocg.MIXED)):
         h = scocg.create_from_problem(p, precision=prec, stream=stream)
         rc, rep = h.solve(p.z, p.rhs_idx, tol=a.tol, max_iter=16, tile=A, zchunk=A,
-                          shift_chunk=A)
+                          shift_chunk=A, cache_mode=A)
         say(f"peapod {name}: tuned tile {rep['tile']} zchunk {rep['zchunk']} shift chunk "
-            f"{rep['shift_chunk']} in {rep['tune_ms']:.0f} ms")
+            f"{rep['shift_chunk']} cache mode {rep['cache_mode']} in {rep['tune_ms']:.0f} ms")
         rc, rep = h.solve(p.z, p.rhs_idx, tol=a.tol, max_iter=capped_iters, tile=A, zchunk=A,
-                          shift_chunk=A, timing=1)
+                          shift_chunk=A, cache_mode=A, timing=1)
         h.destroy()
         assert rc in (scocg.OK, scocg.NOT_ALL_CONVERGED), rc
         r = {"iterations": capped_iters,
@@ -456,7 +457,8 @@ def peapod_large_measure(a, capped_iters=256):
                                          for k in scocg.KERNEL_FAMILIES
                                          if rep["kernel_launches"][k]},
              "launch_shape": {"tile": rep["tile"], "zchunk": rep["zchunk"],
-                              "shift_chunk": rep["shift_chunk"]}}
+                              "shift_chunk": rep["shift_chunk"],
+                              "cache_mode": rep["cache_mode"]}}
         r.update(_capped_rates(p, rep, capped_iters, prec == scocg.FP64))
         res[name] = r
         say(f"peapod {name}: {r['ms_per_iteration']:.2f} ms/iteration; r_(n+1) pass "
@@ -469,11 +471,12 @@ def peapod_large_measure(a, capped_iters=256):
     ks = np.linspace(0, K - 1, 8).round().astype(int)
     q = p.with_(z=p.z[ks], rhs_idx=cols)
     h = scocg.create_from_problem(q, precision=scocg.FP64, stream=stream)
-    h.solve(q.z, q.rhs_idx, tol=a.tol, max_iter=16, tile=A, zchunk=A, shift_chunk=A)
+    h.solve(q.z, q.rhs_idx, tol=a.tol, max_iter=16, tile=A, zchunk=A, shift_chunk=A,
+            cache_mode=A)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     rc, rep = h.solve(q.z, q.rhs_idx, tol=a.tol, max_iter=400000, use_graph=True, tile=A,
-                      zchunk=A, shift_chunk=A)
+                      zchunk=A, shift_chunk=A, cache_mode=A)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t1
     h.destroy()
@@ -550,11 +553,13 @@ def main():
     out = torch.empty((K, R, R), dtype=torch.complex128, device="cuda")
     kw = dict(tol=a.tol, timing=2)
     if a.shape:
-        t_, z_, k_ = (int(x) for x in a.shape.split(","))
-        kw.update(tile=t_, zchunk=z_, shift_chunk=k_)
+        vals = [int(x) for x in a.shape.split(",")]
+        kw.update(tile=vals[0], zchunk=vals[1], shift_chunk=vals[2],
+                  cache_mode=vals[3] if len(vals) > 3 else 0)
         a.fixed_shape = True
     elif not a.fixed_shape:  # autotuned in the first (warmup) solve, cached in the handle
-        kw.update(tile=scocg.AUTO, zchunk=scocg.AUTO, shift_chunk=scocg.AUTO)
+        kw.update(tile=scocg.AUTO, zchunk=scocg.AUTO, shift_chunk=scocg.AUTO,
+                  cache_mode=scocg.AUTO)
     if a.max_iter > 0:
         kw["max_iter"] = a.max_iter
     if a.calibrate_copy_mib > 0:
@@ -570,7 +575,8 @@ def main():
     if not a.fixed_shape:
         rc, rep = h.solve(p.z, p.rhs_idx, **dict(kw, max_iter=16, timing=0))
         say(f"autotuned launch shape: tile {rep['tile']} zchunk {rep['zchunk']} shift chunk "
-            f"{rep['shift_chunk']} ({rep['tune_ms']:.0f} ms of trials)")
+            f"{rep['shift_chunk']} cache mode {rep['cache_mode']} ({rep['tune_ms']:.0f} ms of "
+            f"trials)")
     for i in range(a.warmup):
         rc, rep = h.solve(p.z, p.rhs_idx, **kw)
         h.green_columns(out)
@@ -625,6 +631,7 @@ def main():
                      achieved * traffic / traffic_alg},
         "launch_shape": {"tile": reps[-1]["tile"], "zchunk": reps[-1]["zchunk"],
                          "shift_chunk": reps[-1]["shift_chunk"],
+                         "cache_mode": reps[-1]["cache_mode"],
                          "autotuned": not a.fixed_shape},
         "seed_iters": int(reps[-1]["seed_iters"]),
         "solve_ms_device": float(np.mean([r["solve_ms"] for r in reps])),

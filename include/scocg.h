@@ -143,12 +143,18 @@ typedef struct {
                             mirror column -- about half the shift-vector work.  Needs
                             S = the RHS set (s_idx NULL), full = 0, conventional = 0.  The
                             mirrored entries carry the mirror column's error (same tol) */
+    int32_t cache_mode;  /* cache policy of the r_{n+1} pass: 0 (default) r_{n-1} loads and
+                            r_{n+1} stores nontemporal; 1 r_{n+1} stores ordinary (they stay
+                            in the last-level cache for the next mu pass); 2 both ordinary;
+                            SCOCG_AUTO: autotuned with the launch shape.  Results do not
+                            depend on it */
 } scocg_solve_opts;
 
 /* Autotuning: any of tile, zchunk, shift_chunk = SCOCG_AUTO makes scocg_solve time
    short trial runs (16 seed iterations from the initial state of this very problem)
    of each candidate launch shape -- the 4 tile shapes x up to 8 z-chunk lengths around
-   the default, then 3 shift chunks -- before the solve proper, keep the fastest, and
+   the default, then 3 shift chunks, then 3 cache policies -- before the solve proper,
+   keep the fastest, and
    cache it in the handle for this (column blocks, energies, rows) shape; later solves
    of that shape reuse it.  Trials run outside the timed region (scocg_report.tune_ms
    gives their cost, 0 when cached). */
@@ -184,6 +190,7 @@ typedef struct {
     int32_t shift_chunk_used;
     int32_t tuned;       /* out: 1 if this call ran the autotuning trials */
     double tune_ms;      /* out: device time of the autotuning trials */
+    int32_t cache_mode_used; /* out: cache policy of the r_{n+1} pass (scocg_solve_opts) */
 } scocg_report;
 
 /*

@@ -197,6 +197,8 @@ struct StencilArgs {
   ProjArgs<T> proj;
   int nshift_wg;         // MU: next workgroups doing the previous iteration's x, p update
   ShiftArgs<T> shift;
+  int cache_mode;        // UPDATE: 0 r_{n-1} loads and r_{n+1} stores nontemporal; 1 r_{n+1}
+                         // stores ordinary (the next mu pass reads them); 2 both ordinary
 };
 
 // Component-wise select of two complex values taken by value.  Register arrays
@@ -629,7 +631,9 @@ struct StencilWG {
       const uint32_t zq = (FULL || val[m]) ? (uint32_t)(pz(iz + NF) + NF) : pc;
       pq[m] = ldr(zq, qoff[m]);
       if (MODE == MODE_UPDATE)
-        pp[m] = ld_stream(reinterpret_cast<const cT*>(iobase + pc * pstride + qoff[m]));
+        pp[m] = a.cache_mode < 2
+                    ? ld_stream(reinterpret_cast<const cT*>(iobase + pc * pstride + qoff[m]))
+                    : *reinterpret_cast<const cT*>(iobase + pc * pstride + qoff[m]);
     }
 #pragma unroll
     for (int i = 0; i < HPT; ++i) ph[i] = ldr(pc, hoff[i]);
@@ -781,7 +785,10 @@ struct StencilWG {
           rn.y = __builtin_fma(ap.x, rp.y, rn.y);
           rn.y = __builtin_fma(ap.y, rp.x, rn.y);
           const cT rs = from_d<cT>(rn);
-          st_stream(op, rs);
+          if (a.cache_mode == 0)
+            st_stream(op, rs);
+          else
+            *op = rs;
           const double2 rq = to_d(rs);
           acc0.x = __builtin_fma(rq.x, rq.x, __builtin_fma(-rq.y, rq.y, acc0.x));
           acc0.y = __builtin_fma(2.0 * rq.x, rq.y, acc0.y);

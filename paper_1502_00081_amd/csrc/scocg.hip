@@ -157,6 +157,7 @@ struct scocg_ctx {
     int sym = 0;   // rows below each block's first column are taken from the mirror column
     StencilGrid g{};
     int kch = 4;  // energies per workgroup of k_shift
+    int cache_mode = 0;  // cache policy of the r_{n+1} pass (StencilArgs::cache_mode)
     bool full = false;
     DevBuf r0, r1, z, cols, sh, coef, list, cnt, k5cnt, blk_active, blk_iter, rhs, srow, x, p,
         dc, qa, part0, part1;
@@ -167,7 +168,7 @@ struct scocg_ctx {
   };
   std::unique_ptr<Solve> last;
   // autotuned launch shapes per (B, column blocks, energies, rows): {tile, zchunk, kch}
-  std::map<std::array<int64_t, 4>, std::array<int32_t, 3>> tuned;
+  std::map<std::array<int64_t, 4>, std::array<int32_t, 4>> tuned;
 };
 
 namespace {
@@ -553,6 +554,7 @@ struct Solver {
     S.g = plan(nb, o.tile, o.zchunk);
     S.nwg = S.g.nwg;
     S.kch = o.shift_chunk > 0 ? o.shift_chunk : 4;
+    S.cache_mode = o.cache_mode > 0 ? o.cache_mode : 0;
     const size_t vec = (size_t)nb * bstride() * sizeof(cT);
     S.r0.alloc(vec);
     S.r1.alloc(vec);
@@ -661,7 +663,7 @@ struct Solver {
   // Autotuning: time each candidate stencil shape (tile x z-chunk), then each shift
   // chunk, on this problem; keep the fastest.  Returns the device time spent.
   double tune(const double2* zk, int seed0, const scocg_solve_opts& o, bool want_tile,
-              bool want_zc, bool want_kch) {
+              bool want_zc, bool want_kch, bool want_cache) {
     constexpr int kIters = 16;
     Event a, b;
     HIPCHK(hipEventRecord(a, h.stream));
@@ -710,6 +712,23 @@ struct Solver {
         }
       }
       S.kch = bk;
+    }
+    if (want_cache) {
+      // whole-iteration effect of the r_{n+1} pass's cache policy: nontemporal streams
+      // keep r_n's halo planes in cache within the pass; ordinary stores leave r_{n+1}
+      // in the last-level cache for the mu pass that reads it next
+      double best = INFINITY;
+      int bm = 0;
+      for (int m : {0, 1, 2}) {
+        S.cache_mode = m;
+        const double us = trial(zk, seed0, o, kIters);
+        if (trace_on()) fprintf(stderr, "[scocg] tune cache mode %d: %.1f us/iteration\n", m, us);
+        if (us < best) {
+          best = us;
+          bm = m;
+        }
+      }
+      S.cache_mode = bm;
     }
     HIPCHK(hipEventRecord(b, h.stream));
     return elapsed_ms(a, b);
@@ -890,18 +909,20 @@ struct Solver {
   double autotune(const scocg_solve_opts& o, int* tuned_now) {
     *tuned_now = 0;
     const bool auto_tile = o.tile == SCOCG_AUTO, auto_zc = o.zchunk == SCOCG_AUTO,
-               auto_kch = o.shift_chunk == SCOCG_AUTO;
-    if (!(auto_tile || auto_zc || auto_kch)) return 0.0;
+               auto_kch = o.shift_chunk == SCOCG_AUTO, auto_cache = o.cache_mode == SCOCG_AUTO;
+    if (!(auto_tile || auto_zc || auto_kch || auto_cache)) return 0.0;
     const std::array<int64_t, 4> key{B, S.nb, S.K, S.nS};
     auto it = h.tuned.find(key);
     if (it != h.tuned.end()) {
       set_grid(plan(S.nb, auto_tile ? it->second[0] : o.tile, auto_zc ? it->second[1] : o.zchunk));
       if (auto_kch) S.kch = it->second[2];
+      if (auto_cache) S.cache_mode = it->second[3];
       return 0.0;
     }
-    const double ms = tune(zk.as<double2>(), seed0, o, auto_tile, auto_zc, auto_kch);
+    const double ms =
+        tune(zk.as<double2>(), seed0, o, auto_tile, auto_zc, auto_kch, auto_cache);
     *tuned_now = 1;
-    h.tuned[key] = {S.g.variant, S.g.zc, S.kch};
+    h.tuned[key] = {S.g.variant, S.g.zc, S.kch, S.cache_mode};
     return ms;
   }
 
@@ -989,6 +1010,7 @@ struct Solver {
       rep->tile_used = S.g.variant;
       rep->zchunk_used = S.g.zc;
       rep->shift_chunk_used = S.kch;
+      rep->cache_mode_used = S.cache_mode;
       rep->tuned = tuned_now;
       rep->tune_ms = tune_ms;
     }
@@ -1065,6 +1087,7 @@ struct Batch {
       m.nshift_wg = (m.shift.gx * m.shift.gy * S.nb + 7) / 8 * 8;
       StencilArgs<T> u = p->stencil_args(MODE_UPDATE, S.g, S.nb, cols, act, part0, part1,
                                          S.dc.template as<cT>(), nullptr);
+      u.cache_mode = S.cache_mode;
       for (StencilArgs<T>* q : {&m, &u}) {
         q->pingpong = 1;
         q->bufs[0] = to_g(b0);
@@ -1632,6 +1655,8 @@ scocg_solve_opts check_opts(const scocg_solve_opts* opts) {
   require(o.timing >= 0 && o.timing <= 2, "timing must be 0, 1 or 2");
   require(o.tile >= SCOCG_AUTO && o.tile <= 4, "tile must be SCOCG_AUTO or 0..4");
   require(o.zchunk >= SCOCG_AUTO, "zchunk must be SCOCG_AUTO or >= 0");
+  require(o.cache_mode >= SCOCG_AUTO && o.cache_mode <= 2,
+          "cache_mode must be SCOCG_AUTO, 0, 1 or 2");
   require(o.shift_chunk == SCOCG_AUTO || o.shift_chunk == 0 || o.shift_chunk == 1 ||
               o.shift_chunk == 4 || o.shift_chunk == 16,
           "shift_chunk must be SCOCG_AUTO, 0, 1, 4 or 16");
@@ -1657,7 +1682,7 @@ scocg_solve_opts check_opts(const scocg_solve_opts* opts) {
 // winner is kept in every region's state.  Returns the device ms of the trials.
 template <typename T, int B>
 double tune_batch(std::vector<Solver<T, B>*>& ptr, const scocg_solve_opts& o, bool want_tile,
-                  bool want_kch) {
+                  bool want_kch, bool want_cache) {
   constexpr int kIters = 16;
   hipStream_t st = ptr[0]->h.stream;
   scocg_solve_opts ot = o;
@@ -1712,6 +1737,20 @@ double tune_batch(std::vector<Solver<T, B>*>& ptr, const scocg_solve_opts& o, bo
     }
     for (auto* p : ptr) p->S.kch = bk;
   }
+  if (want_cache) {
+    double best = INFINITY;
+    int bm = 0;
+    for (int m : {0, 1, 2}) {
+      for (auto* p : ptr) p->S.cache_mode = m;
+      const double ms = trial();
+      if (trace_on()) fprintf(stderr, "[scocg] batch tune cache mode %d: %.3f ms\n", m, ms);
+      if (ms < best) {
+        best = ms;
+        bm = m;
+      }
+    }
+    for (auto* p : ptr) p->S.cache_mode = bm;
+  }
   HIPCHK(hipEventRecord(t1, st));
   return elapsed_ms(t0, t1);
 }
@@ -1721,10 +1760,12 @@ int run_batch(int n, const scocg_handle* hs, const scocg_problem* pr, scocg_solv
               scocg_report* reps, double* region_ms) {
   // SCOCG_AUTO: one tile shape and shift chunk for the whole batch, tuned on the batch
   // itself before the timed region; z-chunks stay per region (each region's plan)
-  const bool auto_tile = o.tile == SCOCG_AUTO, auto_kch = o.shift_chunk == SCOCG_AUTO;
+  const bool auto_tile = o.tile == SCOCG_AUTO, auto_kch = o.shift_chunk == SCOCG_AUTO,
+             auto_cache = o.cache_mode == SCOCG_AUTO;
   if (o.tile == SCOCG_AUTO) o.tile = 0;
   if (o.zchunk == SCOCG_AUTO) o.zchunk = 0;
   if (o.shift_chunk == SCOCG_AUTO) o.shift_chunk = 0;
+  if (o.cache_mode == SCOCG_AUTO) o.cache_mode = 0;
   std::vector<std::unique_ptr<Solver<T, B>>> sv;
   std::vector<Solver<T, B>*> ptr;
   for (int i = 0; i < n; ++i) {
@@ -1736,7 +1777,8 @@ int run_batch(int n, const scocg_handle* hs, const scocg_problem* pr, scocg_solv
     ptr.push_back(sv.back().get());
   }
   double tune_ms = 0.0;
-  if (auto_tile || auto_kch) tune_ms = tune_batch<T, B>(ptr, o, auto_tile, auto_kch);
+  if (auto_tile || auto_kch || auto_cache)
+    tune_ms = tune_batch<T, B>(ptr, o, auto_tile, auto_kch, auto_cache);
   hipStream_t st = hs[0]->stream;
   Event e0, e1;
   HIPCHK(hipEventRecord(e0, st));
