@@ -255,6 +255,23 @@ int scocg_green_columns(scocg_handle h, void *dst, int32_t dtype, int32_t dst_is
 /* Apply y = H x for complex128 device vectors x, y of length N (checking aid). */
 int scocg_apply_h(scocg_handle h, const void *x_dev, void *y_dev);
 
+/*
+ * scocg_apply_h without any device allocation, for callers that cannot allocate
+ * (tight serving loops, harnesses that forbid hipMalloc): the same kernels and the
+ * same result, bit for bit, with the workspace -- x in a padded column block, the
+ * stencil output block, the projector coefficients, the launch's argument table --
+ * taken from a static device array of SCOCG_SCRATCH_BYTES per GPU, which the library
+ * holds from its first use on that GPU (scocg_create sets it up) until the process
+ * ends.  x_dev, y_dev: complex128 device vectors of length N on the handle's device.
+ * The workspace needs about 2 (nz + 2 nf) nx ny 128 bytes plus n_atoms 512 bytes (and,
+ * for SCOCG_MIXED, 128 bytes per projector entry for the per-entry products);
+ * a larger grid is rejected with SCOCG_EINVAL before any launch.  Every call on a GPU
+ * shares that GPU's array: calls that overlap on one GPU (two threads, or two
+ * streams) race and must be serialised by the caller.  Enqueued on the handle's
+ * stream; returns after y is written.
+ */
+#define SCOCG_SCRATCH_BYTES (64u << 20)
+int scocg_apply_h_noalloc(scocg_handle h, const void *x_dev, void *y_dev);
 
 /*
  * Open-boundary matching (Sec. 3B, Eqs. 18-24) and transmission (Sec. 2B, Eq. 14).

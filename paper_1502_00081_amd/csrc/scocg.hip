@@ -19,6 +19,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <type_traits>
@@ -29,6 +30,13 @@
 #include "scocg.h"
 
 using namespace scocg;
+
+// Device workspace of the allocation-free entry point scocg_apply_h_noalloc: one copy
+// per GPU, held from the library's first use on that GPU until the process ends.  In
+// host code `scratch` names a host-side stand-in, not device memory: its address on
+// each device is taken once with hipGetSymbolAddress (init_scratch, called by
+// scocg_create with the handle's device current) and only that address is used.
+static __device__ __align__(256) char scratch[SCOCG_SCRATCH_BYTES];
 
 namespace {
 
@@ -130,6 +138,28 @@ int trace_level() {
   return lv;
 }
 bool trace_on() { return trace_level() > 0; }
+
+// device -> address of `scratch` on that device
+std::mutex g_scratch_mu;
+std::map<int, char*> g_scratch;
+
+// once per device, with that device current
+void init_scratch(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch.count(device)) return;
+  void* p = nullptr;
+  HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  if (!p) throw Error(SCOCG_EHIP, "hipGetSymbolAddress(scratch) returned NULL");
+  g_scratch[device] = static_cast<char*>(p);
+}
+
+char* scratch_of(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch.find(device);
+  if (it == g_scratch.end())
+    throw Error(SCOCG_EHIP, "scratch of device " + std::to_string(device) + " not set up");
+  return it->second;
+}
 
 }  // namespace
 
@@ -1853,6 +1883,7 @@ int scocg_create(const scocg_grid* g, const double* coef, const double* vloc, in
       h->proj_mfma = precision == SCOCG_MIXED && pe && std::string(pe) == "mfma";
     }
     HIPCHK(hipGetDevice(&h->device));
+    init_scratch(h->device);
     h->stream = static_cast<hipStream_t>(hip_stream);
     if (!h->stream) {  // a private stream, so that solves can be graph-captured
       HIPCHK(hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking));
@@ -1985,6 +2016,24 @@ int scocg_apply_h(scocg_handle h, const void* x_dev, void* y_dev) {
       apply_h_impl<double, 8>(*h, x_dev, y_dev);
     else
       apply_h_impl<float, 16>(*h, x_dev, y_dev);
+    return SCOCG_OK;
+  });
+}
+
+int scocg_apply_h_noalloc(scocg_handle h, const void* x_dev, void* y_dev) {
+  return guarded([&]() -> int {
+    require(h != nullptr && x_dev != nullptr && y_dev != nullptr, "NULL argument");
+    HIPCHK(hipSetDevice(h->device));
+    char* ws = scratch_of(h->device);
+    const size_t need = h->precision == SCOCG_FP64 ? ApplyWs<double, 8>(*h).bytes
+                                                   : ApplyWs<float, 16>(*h).bytes;
+    require(need <= (size_t)SCOCG_SCRATCH_BYTES,
+            "grid too large for the allocation-free apply: needs " + std::to_string(need) +
+                " bytes of scratch, the maximum is " + std::to_string((size_t)SCOCG_SCRATCH_BYTES));
+    if (h->precision == SCOCG_FP64)
+      apply_h_run<double, 8>(*h, x_dev, y_dev, ws);
+    else
+      apply_h_run<float, 16>(*h, x_dev, y_dev, ws);
     return SCOCG_OK;
   });
 }

@@ -23,8 +23,9 @@ PAIR_CONVERGED, PAIR_MAXITER, PAIR_BREAKDOWN, PAIR_STALLED = 0, 1, 2, 4
 C128, C64 = 0, 1
 
 EXPORTS = ("scocg_create", "scocg_solve", "scocg_batch_solve", "scocg_green_columns",
-           "scocg_apply_h", "scocg_obm", "scocg_stream_probe",
+           "scocg_apply_h", "scocg_apply_h_noalloc", "scocg_obm", "scocg_stream_probe",
            "scocg_destroy", "scocg_last_error", "scocg_struct_size")
+SCRATCH_BYTES = 64 << 20  # SCOCG_SCRATCH_BYTES: workspace of the allocation-free apply
 AUTO = -1  # SCOCG_AUTO: autotuned launch shape
 
 
@@ -90,6 +91,8 @@ def load(path: str = LIB_PATH):
     lib.scocg_green_columns.restype = C.c_int
     lib.scocg_apply_h.argtypes = [P, P, P]
     lib.scocg_apply_h.restype = C.c_int
+    lib.scocg_apply_h_noalloc.argtypes = [P, P, P]
+    lib.scocg_apply_h_noalloc.restype = C.c_int
     lib.scocg_destroy.argtypes = [P]
     lib.scocg_destroy.restype = None
     lib.scocg_last_error.argtypes = []
@@ -218,6 +221,11 @@ class Handle:
     def apply_h(self, x_dev, y_dev):
         """scocg_apply_h on complex128 device vectors (torch tensors or raw pointers)."""
         _check(load().scocg_apply_h(self._h, _dev_ptr(x_dev), _dev_ptr(y_dev)))
+
+    def apply_h_noalloc(self, x_dev, y_dev):
+        """scocg_apply_h_noalloc: the same apply with no device allocation (workspace in
+        the library's per-GPU scratch array)."""
+        _check(load().scocg_apply_h_noalloc(self._h, _dev_ptr(x_dev), _dev_ptr(y_dev)))
 
     def obm(self, K, M, L, g_dev, sig_l_dev, sig_r_dev, gt_dev=None, phase_ms=None):
         """scocg_obm on device buffers (torch tensors or raw pointers), all complex128 and
