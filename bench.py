@@ -66,6 +66,9 @@ def parse():
                     help="skip the mixed-vs-FP64 comparison on a medium column subset")
     ap.add_argument("--no-peapod", action="store_true",
                     help="skip the peapod-shaped 64x64x160 sub-measurement")
+    ap.add_argument("--apply-only", action="store_true",
+                    help="time scocg_apply_h on the workload's operator (30 calls) instead "
+                         "of solving; SCOCG_PROJ=mfma selects the matrix-core projector path")
     return ap.parse_args()
 
 
@@ -82,7 +85,7 @@ def kernel_source_hash():
     return d.hexdigest()[:16]
 
 
-def measured_traffic(workload, precision, tile, zchunk):
+def measured_traffic(workload, precision, tile, zchunk, cache_mode=0):
     """HBM bytes per launch of the r_{n+1} pass from the committed counter summary
     (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's readings); None when the
     summary is missing, covers another workload or launch shape, or the device code
@@ -95,6 +98,7 @@ def measured_traffic(workload, precision, tile, zchunk):
     kv = {k.strip(): v.strip() for k, v in kv.items()}
     if (kv.get("workload") != workload or kv.get("precision") != precision
             or kv.get("tile") != str(tile) or kv.get("zchunk") != str(zchunk)
+            or kv.get("cache_mode", "0") != str(cache_mode)
             or kv.get("kernel_source_sha256_16") != kernel_source_hash()):
         return None, None
     return float(kv["traffic_bytes_per_launch"]), float(kv["algorithmic_bytes_per_launch"])
@@ -208,9 +212,13 @@ def batched_regions_run(a):
     hs = [scocg.create_from_problem(p, precision=prec, stream=stream) for p in regs]
     A = scocg.AUTO
     # launch shapes tuned on the batch (one tile and shift chunk for all regions) and,
-    # for the region-by-region comparison, on each region alone
+    # for the region-by-region comparison, on each region alone; or given by --shape
     kw = dict(tol=a.tol, use_graph=True, max_iter=a.max_iter if a.max_iter > 0 else 400000,
               tile=A, zchunk=A, shift_chunk=A, cache_mode=A)
+    if a.shape:
+        vals = [int(x) for x in a.shape.split(",")]
+        kw.update(tile=vals[0], zchunk=vals[1], shift_chunk=vals[2],
+                  cache_mode=vals[3] if len(vals) > 3 else 0)
     pairs = sum(p.z.size * p.rhs_idx.size for p in regs)
     say(f"batched regions: {len(regs)} regions, {pairs} pairs, precision {a.precision}")
     torch.cuda.synchronize()
@@ -491,6 +499,27 @@ def peapod_large_measure(a, capped_iters=256):
     return res
 
 
+def apply_run(a, p, h, calls=30):
+    """scocg_apply_h on a random complex128 vector, `calls` times (one column block of
+    the operator per call): average wall time per call, and the projector path."""
+    import torch
+    x = torch.randn(p.n, dtype=torch.complex128, device="cuda")
+    y = torch.empty_like(x)
+    h.apply_h(x, y)  # warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(calls):
+        h.apply_h(x, y)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / calls
+    h.destroy()
+    print(json.dumps({"metric": "operator apply time", "value": dt * 1e3, "unit": "ms",
+                      "higher_is_better": False, "calls": calls,
+                      "config": {"workload": p.name, "precision": a.precision,
+                                 "projectors": os.environ.get("SCOCG_PROJ", "valu")}}),
+          flush=True)
+
+
 def copy_bandwidth(nbytes=1 << 30, reps=5):
     """A plain device-to-device copy of nbytes (torch), timed with HIP events over reps
     copies; bytes read + written per second (GB/s)."""
@@ -549,6 +578,9 @@ def main():
     prec = scocg.FP64 if a.precision == "fp64" else scocg.MIXED
     stream = torch.cuda.current_stream()
     h = scocg.create_from_problem(p, precision=prec, stream=stream)
+    if a.apply_only:
+        apply_run(a, p, h)
+        return
     K, R = p.z.size, p.rhs_idx.size
     out = torch.empty((K, R, R), dtype=torch.complex128, device="cuda")
     kw = dict(tol=a.tol, timing=2)
@@ -601,7 +633,7 @@ def main():
     upd_launches = sum(r["kernel_launches"]["update"] for r in reps)
     achieved = upd_bytes / (upd_ms * 1e-3) / 1e9
     traffic, traffic_alg = measured_traffic(p.name, a.precision, reps[-1]["tile"],
-                                            reps[-1]["zchunk"])
+                                            reps[-1]["zchunk"], reps[-1]["cache_mode"])
     line = {
         "metric": "converged (shift x column) solves/s at 1e-8 rel residual",
         "value": converged / dt,
