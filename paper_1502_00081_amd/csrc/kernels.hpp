@@ -116,6 +116,10 @@ struct ShiftCoef {
   int32_t pad_[3];
 };
 
+// Most list entries (energies) a shift workgroup takes; the LDS staging of their
+// coefficients holds SHIFT_KCH_MAX x B records.
+constexpr int SHIFT_KCH_MAX = 16;
+
 enum { ST_CONVERGED = 0, ST_MAXITER = 1, ST_BREAKDOWN = 2, ST_UNUSED = 3, ST_STALLED = 4 };
 
 // Real stencil coefficients, by value in the kernel argument segment.
@@ -854,6 +858,8 @@ void k_stencil(const StencilArgs<T>* __restrict__ regs, const int32_t* __restric
   using cT = typename cplx_of<T>::type;
   constexpr int PROJ_BYTES = 8 * NT * (int)sizeof(T);
   __shared__ __align__(16) char smem[SW::SMEM > PROJ_BYTES ? SW::SMEM : PROJ_BYTES];
+  static_assert(PROJ_BYTES >= SHIFT_KCH_MAX * B * (int)sizeof(ShiftCoef),
+                "the shift workgroups stage their coefficients in this buffer");
   int bid = blockIdx.x;
   const int rg = region_of(off, nreg, bid);
   // a private copy: the compiler keeps the uniform fields in scalar registers instead
@@ -880,7 +886,8 @@ void k_stencil(const StencilArgs<T>* __restrict__ regs, const int32_t* __restric
     // the previous iteration's x, p update (parity cur ^ 1): it reads r_n[S], which
     // this pass only reads, and x, p, which no other workgroup touches
     if (bid < a.nshift_wg) {
-      if (bid < a.shift.gx * a.shift.gy * a.shift.nb) shift_body<T, B, NT>(a.shift, bid, cur ^ 1);
+      if (bid < a.shift.gx * a.shift.gy * a.shift.nb)
+        shift_body<T, B, NT>(a.shift, bid, cur ^ 1, smem);
       return;
     }
     bid -= a.nshift_wg;
@@ -1270,37 +1277,65 @@ __global__ __launch_bounds__(CT) void k_control(const ControlArgs* __restrict__ 
 // grid: (ceil(nS*B/WG), ceil(K/KCH), nb); each thread owns one (row of S, column)
 // and walks a chunk of the block's active shift list.
 
+// One (energy, row, column) update with its coefficients; explicit FMAs, so that every
+// instance (and full and projected storage) rounds alike.
+template <bool NT, typename cT>
+__device__ __forceinline__ void shift_one(double2* __restrict__ x, cT* __restrict__ p, int64_t vo,
+                                          const ShiftCoef& cf, double2 xv, double2 pv,
+                                          double2 rv) {
+  double2 xn, t, pn;
+  xn.x = __builtin_fma(cf.a.x, pv.x, __builtin_fma(-cf.a.y, pv.y, xv.x));
+  xn.y = __builtin_fma(cf.a.x, pv.y, __builtin_fma(cf.a.y, pv.x, xv.y));
+  t.x = __builtin_fma(cf.b.x, pv.x, -(cf.b.y * pv.y));
+  t.y = __builtin_fma(cf.b.x, pv.y, cf.b.y * pv.x);
+  pn.x = __builtin_fma(cf.f.x, rv.x, __builtin_fma(-cf.f.y, rv.y, t.x));
+  pn.y = __builtin_fma(cf.f.x, rv.y, __builtin_fma(cf.f.y, rv.x, t.y));
+  if (NT) {
+    st_stream(x + vo, xn);
+    st_stream(p + vo, from_d<cT>(pn));
+  } else {
+    x[vo] = xn;
+    p[vo] = from_d<cT>(pn);
+  }
+}
+
 // The energy loop of one thread (row i of S, column c): x, p updates of the list
-// entries e0..e1-1.  NT: nontemporal x, p (they do not fit the last-level cache).
+// entries e0..e1-1, two entries at a time so that four loads are in flight.  sc holds
+// the coefficients of the entries, [e - e0][B], staged in LDS by the workgroup.
+// NT: nontemporal x, p (they do not fit the last-level cache).
 template <bool NT, int B, typename T>
-__device__ __forceinline__ void shift_loop(const ShiftArgs<T>& a, const int32_t* l, int e0,
-                                           int e1, int cb, int i, int c, double2 rv) {
+__device__ __forceinline__ void shift_loop(const ShiftArgs<T>& a, const int32_t* l,
+                                           const ShiftCoef* sc, int e0, int e1, int cb, int i,
+                                           int c, double2 rv) {
   using cT = typename cplx_of<T>::type;
-  const int nS = a.nS, K = a.K;
   double2* __restrict__ x = a.x;
   cT* __restrict__ p = a.p;
-  for (int e = e0; e < e1; ++e) {
-    const int k = l[e];
-    const int64_t so = ((int64_t)cb * K + k) * B + c;
-    const ShiftCoef cf = a.coef[so];
-    if (!cf.upd) continue;
-    const int64_t vo = (((int64_t)cb * K + k) * nS + i) * B + c;
-    const double2 xv = NT ? ld_stream(x + vo) : x[vo];
-    const double2 pv = to_d(NT ? ld_stream(p + vo) : p[vo]);
-    // explicit FMAs: both instances (and full and projected storage) round alike
-    double2 xn, t, pn;
-    xn.x = __builtin_fma(cf.a.x, pv.x, __builtin_fma(-cf.a.y, pv.y, xv.x));
-    xn.y = __builtin_fma(cf.a.x, pv.y, __builtin_fma(cf.a.y, pv.x, xv.y));
-    t.x = __builtin_fma(cf.b.x, pv.x, -(cf.b.y * pv.y));
-    t.y = __builtin_fma(cf.b.x, pv.y, cf.b.y * pv.x);
-    pn.x = __builtin_fma(cf.f.x, rv.x, __builtin_fma(-cf.f.y, rv.y, t.x));
-    pn.y = __builtin_fma(cf.f.x, rv.y, __builtin_fma(cf.f.y, rv.x, t.y));
-    if (NT) {
-      st_stream(x + vo, xn);
-      st_stream(p + vo, from_d<cT>(pn));
-    } else {
-      x[vo] = xn;
-      p[vo] = from_d<cT>(pn);
+  const int64_t kstride = (int64_t)a.nS * B, rc = (int64_t)i * B + c, kb = (int64_t)cb * a.K;
+  int e = e0;
+  for (; e + 1 < e1; e += 2) {
+    const ShiftCoef* s0 = sc + (e - e0) * B + c;
+    const ShiftCoef* s1 = s0 + B;
+    const int u0 = s0->upd, u1 = s1->upd;
+    const int64_t v0 = (kb + l[e]) * kstride + rc, v1 = (kb + l[e + 1]) * kstride + rc;
+    double2 x0 = mk(0, 0), x1 = mk(0, 0), p0 = mk(0, 0), p1 = mk(0, 0);
+    if (u0) {
+      x0 = NT ? ld_stream(x + v0) : x[v0];
+      p0 = to_d(NT ? ld_stream(p + v0) : p[v0]);
+    }
+    if (u1) {
+      x1 = NT ? ld_stream(x + v1) : x[v1];
+      p1 = to_d(NT ? ld_stream(p + v1) : p[v1]);
+    }
+    if (u0) shift_one<NT>(x, p, v0, *s0, x0, p0, rv);
+    if (u1) shift_one<NT>(x, p, v1, *s1, x1, p1, rv);
+  }
+  if (e < e1) {
+    const ShiftCoef* s0 = sc + (e - e0) * B + c;
+    if (s0->upd) {
+      const int64_t v0 = (kb + l[e]) * kstride + rc;
+      const double2 x0 = NT ? ld_stream(x + v0) : x[v0];
+      const double2 p0 = to_d(NT ? ld_stream(p + v0) : p[v0]);
+      shift_one<NT>(x, p, v0, *s0, x0, p0, rv);
     }
   }
 }
@@ -1308,17 +1343,25 @@ __device__ __forceinline__ void shift_loop(const ShiftArgs<T>& a, const int32_t*
 // x^(k) += alpha^(k) p^(k);  p^(k) = r_{n+1}[S] / pi^(k)_{n+1} + beta^(k) p^(k)  (Eqs. A11-A12)
 // for workgroup lb of one region (NTH threads): gx * gy * nb workgroups, NTH rows of S
 // x kch list entries x column block.  par: parity of the iteration being completed.
+// smem: at least SHIFT_KCH_MAX * B * sizeof(ShiftCoef) bytes; every thread of the
+// workgroup must call this (it holds a barrier).
 template <typename T, int B, int NTH>
-__device__ __forceinline__ void shift_body(const ShiftArgs<T>& a, int lb, int par) {
+__device__ __forceinline__ void shift_body(const ShiftArgs<T>& a, int lb, int par, char* smem) {
   using cT = typename cplx_of<T>::type;
   const int bx = lb % a.gx, by = (lb / a.gx) % a.gy, cb = lb / (a.gx * a.gy);
   const int cnt = a.k5cnt[cb];
   const int e0 = by * a.kch;
-  if (e0 >= cnt) return;
+  if (e0 >= cnt) return;  // uniform
   const int e1 = min(e0 + a.kch, cnt);
-  const int nS = a.nS, K = a.K;
+  const int K = a.K;
+  const int32_t* l = a.list + ((int64_t)par * a.nb + cb) * K;
+  // the chunk's coefficients are the same for every row: stage them once
+  ShiftCoef* sc = reinterpret_cast<ShiftCoef*>(smem);
+  for (int t = threadIdx.x; t < (e1 - e0) * B; t += NTH)
+    sc[t] = a.coef[((int64_t)cb * K + l[e0 + t / B]) * B + t % B];
+  __syncthreads();
   const int64_t gid = (int64_t)bx * NTH + threadIdx.x;
-  if (gid >= (int64_t)nS * B) return;
+  if (gid >= (int64_t)a.nS * B) return;
   const int i = (int)(gid / B), c = (int)(gid % B);
   // complex symmetry: rows below the block's first column are the mirror of columns
   // already kept by an earlier block, G(S_i, e_j) = G(S_j, e_i)
@@ -1326,11 +1369,10 @@ __device__ __forceinline__ void shift_body(const ShiftArgs<T>& a, int lb, int pa
   const int64_t row = a.srow ? (int64_t)a.srow[i] : (int64_t)i;
   const cT* rnew = par ? a.rnew[0] : a.rnew[1];  // r_{n+1}: buffer par ^ 1
   const double2 rv = to_d(rnew[(int64_t)cb * a.bstride + row * B + c]);
-  const int32_t* l = a.list + ((int64_t)par * a.nb + cb) * K;
   if (a.nt)
-    shift_loop<true, B, T>(a, l, e0, e1, cb, i, c, rv);
+    shift_loop<true, B, T>(a, l, sc, e0, e1, cb, i, c, rv);
   else
-    shift_loop<false, B, T>(a, l, e0, e1, cb, i, c, rv);
+    shift_loop<false, B, T>(a, l, sc, e0, e1, cb, i, c, rv);
 }
 
 // Stand-alone x, p update of the last iteration of a solve (every other iteration's
@@ -1339,9 +1381,10 @@ template <typename T, int B>
 __global__ __launch_bounds__(WG) void k_shift(const ShiftArgs<T>* __restrict__ regs,
                                                const int32_t* __restrict__ off, int nreg,
                                                int par) {
+  __shared__ __align__(16) char smem[SHIFT_KCH_MAX * B * sizeof(ShiftCoef)];
   const int rg = region_of(off, nreg, blockIdx.x);
   const ShiftArgs<T> a = regs[rg];
-  shift_body<T, B, WG>(a, blockIdx.x - off[rg], par);
+  shift_body<T, B, WG>(a, blockIdx.x - off[rg], par, smem);
 }
 
 // ------------------------------------------------------------------ initialisation

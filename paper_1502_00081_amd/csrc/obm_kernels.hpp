@@ -162,6 +162,7 @@ __global__ __launch_bounds__(256) void k_obm_init(const double2* __restrict__ g,
 // tiles, so each element is read and written once per panel instead of once per
 // pivot.  A zero or non-finite pivot marks the energy failed; later kernels skip it.
 constexpr int GJ_W = 32;     // pivots per panel
+constexpr int GJ_EB = 8;     // panel columns of a row loaded together in the elimination
 // threads of the panel kernel: 512, or 1024 above n = 1024 rows (chosen at launch)
 
 // Vj [K][GJ_W][ncol]: row j0 + jj of every column right of the panel, as it stands
@@ -262,23 +263,34 @@ __global__ __launch_bounds__(GJ_PNT) void k_gj_panel(double2* W, double2* F, dou
     for (int i = tid; i < n; i += GJ_PNT) {
       const double2 fi = (i == j) ? double2{0.0, 0.0} : Wk[i + (size_t)n * j];
       Fk[i + (size_t)n * jj] = fi;
-      for (int c = j + 1; c < jend; ++c) {
-        const double2 pj = cmul(s_prow[c - j0], inv);
-        double2* a = Wk + i + (size_t)n * c;
-        double2 v;
-        if (i == j) {
-          v = pj;
-        } else {
-          v = *a;
-          v.x = fma(-fi.x, pj.x, fma(fi.y, pj.y, v.x));
-          v.y = fma(-fi.x, pj.y, fma(-fi.y, pj.x, v.y));
-        }
-        *a = v;
-        if (c == j + 1 && i > j) {
-          const double m = cabs2(v);
-          if (m > best) {
-            best = m;
-            bi = i;
+      // the row's panel columns in batches of GJ_EB: all loads of a batch are issued
+      // before its first store, so a row costs a few memory round trips, not one per
+      // column
+      for (int cb = j + 1; cb < jend; cb += GJ_EB) {
+        double2 v[GJ_EB];
+#pragma unroll
+        for (int q = 0; q < GJ_EB; ++q)
+          v[q] = (cb + q < jend && i != j) ? Wk[i + (size_t)n * (cb + q)] : double2{0.0, 0.0};
+#pragma unroll
+        for (int q = 0; q < GJ_EB; ++q) {
+          const int c = cb + q;
+          if (c >= jend) continue;
+          const double2 pj = cmul(s_prow[c - j0], inv);
+          double2 r;
+          if (i == j) {
+            r = pj;
+          } else {
+            r = v[q];
+            r.x = fma(-fi.x, pj.x, fma(fi.y, pj.y, r.x));
+            r.y = fma(-fi.x, pj.y, fma(-fi.y, pj.x, r.y));
+          }
+          Wk[i + (size_t)n * c] = r;
+          if (c == j + 1 && i > j) {
+            const double m = cabs2(r);
+            if (m > best) {
+              best = m;
+              bi = i;
+            }
           }
         }
       }
@@ -335,14 +347,18 @@ __global__ __launch_bounds__(64) void k_gj_sweep(double2* Vj, const double2* __r
 }
 
 // Update of the columns right of the panel as a tiled product: workgroup (column tile,
-// row tile, energy) owns a GJ_T x GJ_T tile of W.  With the swept panel rows z of its
-// columns (Vj) and the multiplier rows of its tile in LDS -- the lower multipliers of
-// the panel rows zeroed, so those rows start from z and take only the upper terms --
-// each thread updates 4 x 4 elements:
+// row tile, energy) owns a GJ_T x GJ_T tile of W.  The swept panel rows z of its
+// columns (Vj) and the multiplier rows of its tile pass through LDS GJ_KC pivots at a
+// time (34 KB, so that four workgroups share a CU and one's loads overlap another's
+// arithmetic) -- the lower multipliers of the panel rows zeroed, so those rows start
+// from z and take only the upper terms -- and each thread updates 4 x 4 elements:
 //   rows of the panel:  z_j - sum_{j' > j} f^(j')_j z_j';   other rows:  v_i - sum_j' f^(j')_i z_j'.
 // Subtracting a zeroed term leaves a finite value bit for bit unchanged, so this equals
-// the row-by-row update.
-constexpr int GJ_T = 64;  // rows and columns per workgroup tile of the update
+// the row-by-row update.  (The same product on the FP64 matrix cores,
+// v_mfma_f64_16x16x4f64, was slower here: their peak on this chip is the vector peak,
+// and the 64 KB of operands per workgroup halved the workgroups per CU.)
+constexpr int GJ_T = 64;   // rows and columns per workgroup tile of the update
+constexpr int GJ_KC = 16;  // pivots per LDS stage of the update
 
 __global__ __launch_bounds__(256) void k_gj_update(double2* W, const double2* __restrict__ F,
                                                    const double2* __restrict__ Vj,
@@ -355,22 +371,10 @@ __global__ __launch_bounds__(256) void k_gj_update(double2* W, const double2* __
   if (c0 >= ncol || r0 >= n) return;
   double2* Wk = W + (size_t)k * n * ncol;
   const double2* Fk = F + (size_t)k * n * GJ_W;
-  __shared__ double2 zs[GJ_W][GJ_T + 1];  // swept panel rows of the tile's columns
-  __shared__ double2 fs[GJ_T][GJ_W + 1];  // multipliers of the tile's rows
+  const double2* Vk = Vj + (size_t)k * GJ_W * ncol;
+  __shared__ double2 zs[GJ_KC][GJ_T + 1];  // swept panel rows kc.. of the tile's columns
+  __shared__ double2 fs[GJ_T][GJ_KC + 1];  // multipliers kc.. of the tile's rows
   const int tid = threadIdx.x;
-  for (int e = tid; e < w * GJ_T; e += 256) {
-    const int c = e % GJ_T, i = e / GJ_T;
-    zs[i][c] = c0 + c < ncol ? Vj[((size_t)k * GJ_W + i) * ncol + c0 + c] : double2{0.0, 0.0};
-  }
-  for (int e = tid; e < GJ_T * GJ_W; e += 256) {
-    const int r = e % GJ_T, jp = e / GJ_T;
-    const int i = r0 + r;
-    double2 f = {0.0, 0.0};
-    // panel rows take only the multipliers of later pivots
-    if (i < n && jp < w && !(i >= j0 && i < j0 + w && jp <= i - j0)) f = Fk[i + (size_t)n * jp];
-    fs[r][jp] = f;
-  }
-  __syncthreads();
   const int tx = tid & 15, ty = tid >> 4;
   double2 acc[4][4];
 #pragma unroll
@@ -379,24 +383,41 @@ __global__ __launch_bounds__(256) void k_gj_update(double2* W, const double2* __
     const bool in_panel = i >= j0 && i < j0 + w;
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
-      const int c = ty + 16 * b;
-      acc[a][b] = (i >= n || c0 + c >= ncol) ? double2{0.0, 0.0}
-                  : (in_panel ? zs[i - j0][c] : Wk[i + (size_t)n * (c0 + c)]);
+      const int c = c0 + ty + 16 * b;
+      acc[a][b] = (i >= n || c >= ncol) ? double2{0.0, 0.0}
+                  : (in_panel ? Vk[(size_t)(i - j0) * ncol + c] : Wk[i + (size_t)n * c]);
     }
   }
-  for (int jp = 0; jp < w; ++jp) {
-    double2 f[4], z[4];
+  for (int kc = 0; kc < w; kc += GJ_KC) {
+    const int kw = min(GJ_KC, w - kc);
+    if (kc > 0) __syncthreads();  // the previous stage's readers are done
+    for (int e = tid; e < kw * GJ_T; e += 256) {
+      const int c = e % GJ_T, i = e / GJ_T;
+      zs[i][c] = c0 + c < ncol ? Vk[(size_t)(kc + i) * ncol + c0 + c] : double2{0.0, 0.0};
+    }
+    for (int e = tid; e < GJ_T * kw; e += 256) {
+      const int r = e % GJ_T, jq = e / GJ_T, jp = kc + jq;
+      const int i = r0 + r;
+      double2 f = {0.0, 0.0};
+      // panel rows take only the multipliers of later pivots
+      if (i < n && !(i >= j0 && i < j0 + w && jp <= i - j0)) f = Fk[i + (size_t)n * jp];
+      fs[r][jq] = f;
+    }
+    __syncthreads();
+    for (int jq = 0; jq < kw; ++jq) {
+      double2 f[4], z[4];
 #pragma unroll
-    for (int a = 0; a < 4; ++a) f[a] = fs[tx + 16 * a][jp];
+      for (int a = 0; a < 4; ++a) f[a] = fs[tx + 16 * a][jq];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) z[b] = zs[jp][ty + 16 * b];
+      for (int b = 0; b < 4; ++b) z[b] = zs[jq][ty + 16 * b];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+      for (int a = 0; a < 4; ++a)
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        acc[a][b].x = fma(-f[a].x, z[b].x, fma(f[a].y, z[b].y, acc[a][b].x));
-        acc[a][b].y = fma(-f[a].x, z[b].y, fma(-f[a].y, z[b].x, acc[a][b].y));
-      }
+        for (int b = 0; b < 4; ++b) {
+          acc[a][b].x = fma(-f[a].x, z[b].x, fma(f[a].y, z[b].y, acc[a][b].x));
+          acc[a][b].y = fma(-f[a].x, z[b].y, fma(-f[a].y, z[b].x, acc[a][b].y));
+        }
+    }
   }
 #pragma unroll
   for (int a = 0; a < 4; ++a) {

@@ -376,6 +376,7 @@ struct Solver {
 
   // x^(k), p^(k) update arguments for workgroups of nth threads, kch energies each
   ShiftArgs<T> shift_args(int nth, int kch) const {
+    require(kch >= 1 && kch <= SHIFT_KCH_MAX, "shift chunk outside the staged coefficient range");
     ShiftArgs<T> sa{};
     sa.rnew[0] = to_g(plane0(S.r0.template as<cT>()));
     sa.rnew[1] = to_g(plane0(S.r1.template as<cT>()));
