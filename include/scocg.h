@@ -157,7 +157,18 @@ typedef struct {
    keep the fastest, and
    cache it in the handle for this (column blocks, energies, rows) shape; later solves
    of that shape reuse it.  Trials run outside the timed region (scocg_report.tune_ms
-   gives their cost, 0 when cached). */
+   gives their cost, 0 when cached).
+   Persistent records: when the environment variable SCOCG_TUNE_CACHE names a file, a
+   shape tuned by scocg_solve is also appended to it as one JSON line, e.g.
+     {"arch": "gfx950", "precision": "fp64", "grid": [48, 48, 96], "nf": 4, "atoms": 40,
+      "block_width": 8, "blocks": 8, "energies": 128, "rows": 64, "tile": 1,
+      "zchunk": 18, "shift_chunk": 16, "cache_mode": 0}
+   (on one line), and a solve whose handle has no entry for its shape takes the last
+   matching record of the file instead of running the trials (scocg_report.tuned = 0).
+   Only lines in the exact form written here are read; records with values outside
+   the ranges of the options are ignored; a file that cannot be opened is skipped.
+   Appends are single writes in append mode, so processes may share one file.
+   scocg_batch_solve tunes per batch and does not use the file. */
 #define SCOCG_AUTO (-1)
 
 /* kernel families of one seed iteration (index into scocg_report.kernel_ms) */

@@ -8,7 +8,9 @@
 // every (shift, column) pair has frozen, polling one flag array per
 // `poll_every` iterations; the polled iterations can be replayed as one
 // captured hipGraph.
+#include <fcntl.h>
 #include <hip/hip_runtime.h>
+#include <unistd.h>
 
 #include <algorithm>
 #include <array>
@@ -173,6 +175,7 @@ struct scocg_ctx {
   int64_t N = 0;
   int n_atoms = 0;
   int proj_mfma = 0;  // complex64 columns: projector contraction on FP32 matrix cores
+  std::string arch;   // device architecture (gcnArchName up to the first ':')
   std::vector<double> coef;  // [3][nf+1]
   // operator arrays on the device (T = double or float by precision)
   DevBuf vloc, aptr, aidx, aval, aD, prow, patom, pval, pent;
@@ -284,6 +287,74 @@ void upload_operator64(scocg_ctx& h, const double* vloc, const int64_t* atom_ptr
   upload(h.aval64, av, s);
   upload(h.aD64, ad, s);
   upload(h.pval64, pv, s);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Persistent autotuning records.  With SCOCG_TUNE_CACHE naming a file, a tuned launch
+// shape is appended there as one JSON object per line, keyed by the device
+// architecture, precision, grid, nf, atoms, block width, column blocks, energies and
+// rows; a later solve of a shape with a record (in any process) takes it instead of
+// running the trials.  The library reads only lines in the exact form it writes; the
+// last matching record wins; records with values outside the option ranges are
+// ignored.  Appends are single write() calls on an O_APPEND descriptor.
+struct TuneKey {
+  std::string arch;
+  int precision, nx, ny, nz, nf, atoms;
+  int64_t B, nb, K, nS;
+};
+
+std::string tune_key_text(const TuneKey& k) {
+  char buf[512];
+  snprintf(buf, sizeof buf,
+           "{\"arch\": \"%s\", \"precision\": \"%s\", \"grid\": [%d, %d, %d], \"nf\": %d, "
+           "\"atoms\": %d, \"block_width\": %lld, \"blocks\": %lld, \"energies\": %lld, "
+           "\"rows\": %lld, ",
+           k.arch.c_str(), k.precision == SCOCG_FP64 ? "fp64" : "mixed", k.nx, k.ny, k.nz,
+           k.nf, k.atoms, (long long)k.B, (long long)k.nb, (long long)k.K, (long long)k.nS);
+  return buf;
+}
+
+bool tune_record_valid(const std::array<int32_t, 4>& v, int nz) {
+  return v[0] >= 1 && v[0] <= 4 && v[1] >= 1 && v[1] <= nz &&
+         (v[2] == 1 || v[2] == 4 || v[2] == 16) && v[3] >= 0 && v[3] <= 2;
+}
+
+bool tune_cache_lookup(const char* path, const TuneKey& k, std::array<int32_t, 4>* out) {
+  FILE* f = fopen(path, "r");
+  if (!f) return false;
+  const std::string key = tune_key_text(k);
+  bool found = false;
+  char line[1024];
+  while (fgets(line, sizeof line, f)) {
+    if (strncmp(line, key.c_str(), key.size()) != 0) continue;
+    std::array<int32_t, 4> v{};
+    char tail = 0;
+    if (sscanf(line + key.size(),
+               "\"tile\": %d, \"zchunk\": %d, \"shift_chunk\": %d, \"cache_mode\": %d%c", &v[0],
+               &v[1], &v[2], &v[3], &tail) == 5 &&
+        tail == '}' && tune_record_valid(v, k.nz)) {
+      *out = v;
+      found = true;
+    }
+  }
+  fclose(f);
+  return found;
+}
+
+void tune_cache_append(const char* path, const TuneKey& k, const std::array<int32_t, 4>& v) {
+  char buf[128];
+  snprintf(buf, sizeof buf, "\"tile\": %d, \"zchunk\": %d, \"shift_chunk\": %d, \"cache_mode\": %d}\n",
+           v[0], v[1], v[2], v[3]);
+  const std::string line = tune_key_text(k) + buf;
+  const int fd = open(path, O_WRONLY | O_APPEND | O_CREAT, 0644);
+  if (fd < 0) {
+    if (trace_on()) fprintf(stderr, "[scocg] tune cache %s: cannot open for append\n", path);
+    return;
+  }
+  const ssize_t w = write(fd, line.data(), line.size());
+  if (w != (ssize_t)line.size() && trace_on())
+    fprintf(stderr, "[scocg] tune cache %s: short write\n", path);
+  close(fd);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -944,6 +1015,13 @@ struct Solver {
     if (!(auto_tile || auto_zc || auto_kch || auto_cache)) return 0.0;
     const std::array<int64_t, 4> key{B, S.nb, S.K, S.nS};
     auto it = h.tuned.find(key);
+    const char* file = getenv("SCOCG_TUNE_CACHE");
+    const bool use_file = file && *file;
+    const TuneKey tk{h.arch, h.precision, h.nx, h.ny, h.nz, h.nf, h.n_atoms, B, S.nb, S.K, S.nS};
+    if (it == h.tuned.end() && use_file) {
+      std::array<int32_t, 4> rec{};
+      if (tune_cache_lookup(file, tk, &rec)) it = h.tuned.emplace(key, rec).first;
+    }
     if (it != h.tuned.end()) {
       set_grid(plan(S.nb, auto_tile ? it->second[0] : o.tile, auto_zc ? it->second[1] : o.zchunk));
       if (auto_kch) S.kch = it->second[2];
@@ -954,6 +1032,7 @@ struct Solver {
         tune(zk.as<double2>(), seed0, o, auto_tile, auto_zc, auto_kch, auto_cache);
     *tuned_now = 1;
     h.tuned[key] = {S.g.variant, S.g.zc, S.kch, S.cache_mode};
+    if (use_file) tune_cache_append(file, tk, h.tuned[key]);
     return ms;
   }
 
@@ -1885,6 +1964,13 @@ int scocg_create(const scocg_grid* g, const double* coef, const double* vloc, in
     }
     HIPCHK(hipGetDevice(&h->device));
     init_scratch(h->device);
+    {
+      hipDeviceProp_t prop;
+      HIPCHK(hipGetDeviceProperties(&prop, h->device));
+      h->arch = prop.gcnArchName;
+      const size_t colon = h->arch.find(':');
+      if (colon != std::string::npos) h->arch.resize(colon);
+    }
     h->stream = static_cast<hipStream_t>(hip_stream);
     if (!h->stream) {  // a private stream, so that solves can be graph-captured
       HIPCHK(hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking));
