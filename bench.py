@@ -54,7 +54,7 @@ def parse():
     ap.add_argument("--fixed-shape", action="store_true",
                     help="default launch shape instead of the autotuned one")
     ap.add_argument("--shape", default="",
-                    help="explicit launch shape 'tile,zchunk,shift_chunk[,cache_mode]' (no "
+                    help="explicit launch shape 'tile,zchunk,shift_chunk[,cache_mode[,zchunk_mu]]' (no "
                          "autotuning)")
     ap.add_argument("--no-sequential", action="store_true",
                     help="batched_regions: skip the region-by-region comparison")
@@ -218,7 +218,8 @@ def batched_regions_run(a):
     if a.shape:
         vals = [int(x) for x in a.shape.split(",")]
         kw.update(tile=vals[0], zchunk=vals[1], shift_chunk=vals[2],
-                  cache_mode=vals[3] if len(vals) > 3 else 0)
+                  cache_mode=vals[3] if len(vals) > 3 else 0,
+                  zchunk_mu=vals[4] if len(vals) > 4 else 0)
     pairs = sum(p.z.size * p.rhs_idx.size for p in regs)
     say(f"batched regions: {len(regs)} regions, {pairs} pairs, precision {a.precision}")
     torch.cuda.synchronize()
@@ -333,7 +334,7 @@ def obm_measure(a, steps, warmup, wide=False):
     say(f"obm wire: N={p.n}, K={K}, M={M}, L={L}, D={D}")
     tol = 1e-10
     kw = dict(tol=tol, use_graph=True, tile=scocg.AUTO, zchunk=scocg.AUTO,
-              shift_chunk=scocg.AUTO, symmetric=not a.no_symmetric)
+              shift_chunk=scocg.AUTO, zchunk_mu=scocg.AUTO, symmetric=not a.no_symmetric)
     rc, rep = h.solve(p.z, p.rhs_idx, **dict(kw, max_iter=16))  # autotune, cached in the handle
     say(f"autotuned launch shape: tile {rep['tile']} zchunk {rep['zchunk']} shift chunk "
         f"{rep['shift_chunk']}")
@@ -452,11 +453,12 @@ def peapod_large_measure(a, capped_iters=256):
     for name, prec in (("capped_fp64", scocg.FP64), ("capped_mixed", scocg.MIXED)):
         h = scocg.create_from_problem(p, precision=prec, stream=stream)
         rc, rep = h.solve(p.z, p.rhs_idx, tol=a.tol, max_iter=16, tile=A, zchunk=A,
-                          shift_chunk=A, cache_mode=A)
-        say(f"peapod {name}: tuned tile {rep['tile']} zchunk {rep['zchunk']} shift chunk "
-            f"{rep['shift_chunk']} cache mode {rep['cache_mode']} in {rep['tune_ms']:.0f} ms")
+                          shift_chunk=A, cache_mode=A, zchunk_mu=A)
+        say(f"peapod {name}: tuned tile {rep['tile']} zchunk {rep['zchunk']} (mu pass "
+            f"{rep['zchunk_mu']}) shift chunk {rep['shift_chunk']} cache mode "
+            f"{rep['cache_mode']} in {rep['tune_ms']:.0f} ms")
         rc, rep = h.solve(p.z, p.rhs_idx, tol=a.tol, max_iter=capped_iters, tile=A, zchunk=A,
-                          shift_chunk=A, cache_mode=A, timing=1)
+                          shift_chunk=A, cache_mode=A, zchunk_mu=A, timing=1)
         h.destroy()
         assert rc in (scocg.OK, scocg.NOT_ALL_CONVERGED), rc
         r = {"iterations": capped_iters,
@@ -465,6 +467,7 @@ def peapod_large_measure(a, capped_iters=256):
                                          for k in scocg.KERNEL_FAMILIES
                                          if rep["kernel_launches"][k]},
              "launch_shape": {"tile": rep["tile"], "zchunk": rep["zchunk"],
+                              "zchunk_mu": rep["zchunk_mu"],
                               "shift_chunk": rep["shift_chunk"],
                               "cache_mode": rep["cache_mode"]}}
         r.update(_capped_rates(p, rep, capped_iters, prec == scocg.FP64))
@@ -480,11 +483,11 @@ def peapod_large_measure(a, capped_iters=256):
     q = p.with_(z=p.z[ks], rhs_idx=cols)
     h = scocg.create_from_problem(q, precision=scocg.FP64, stream=stream)
     h.solve(q.z, q.rhs_idx, tol=a.tol, max_iter=16, tile=A, zchunk=A, shift_chunk=A,
-            cache_mode=A)
+            cache_mode=A, zchunk_mu=A)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     rc, rep = h.solve(q.z, q.rhs_idx, tol=a.tol, max_iter=400000, use_graph=True, tile=A,
-                      zchunk=A, shift_chunk=A, cache_mode=A)
+                      zchunk=A, shift_chunk=A, cache_mode=A, zchunk_mu=A)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t1
     h.destroy()
@@ -587,11 +590,12 @@ def main():
     if a.shape:
         vals = [int(x) for x in a.shape.split(",")]
         kw.update(tile=vals[0], zchunk=vals[1], shift_chunk=vals[2],
-                  cache_mode=vals[3] if len(vals) > 3 else 0)
+                  cache_mode=vals[3] if len(vals) > 3 else 0,
+                  zchunk_mu=vals[4] if len(vals) > 4 else 0)
         a.fixed_shape = True
     elif not a.fixed_shape:  # autotuned in the first (warmup) solve, cached in the handle
         kw.update(tile=scocg.AUTO, zchunk=scocg.AUTO, shift_chunk=scocg.AUTO,
-                  cache_mode=scocg.AUTO)
+                  cache_mode=scocg.AUTO, zchunk_mu=scocg.AUTO)
     if a.max_iter > 0:
         kw["max_iter"] = a.max_iter
     if a.calibrate_copy_mib > 0:
@@ -606,9 +610,9 @@ def main():
     say(f"workload {p.name}: N={p.n}, K={K}, R={R}, precision {a.precision}")
     if not a.fixed_shape:
         rc, rep = h.solve(p.z, p.rhs_idx, **dict(kw, max_iter=16, timing=0))
-        say(f"autotuned launch shape: tile {rep['tile']} zchunk {rep['zchunk']} shift chunk "
-            f"{rep['shift_chunk']} cache mode {rep['cache_mode']} ({rep['tune_ms']:.0f} ms of "
-            f"trials)")
+        say(f"autotuned launch shape: tile {rep['tile']} zchunk {rep['zchunk']} (mu pass "
+            f"{rep['zchunk_mu']}) shift chunk {rep['shift_chunk']} cache mode {rep['cache_mode']} "
+            f"({rep['tune_ms']:.0f} ms of trials)")
     for i in range(a.warmup):
         rc, rep = h.solve(p.z, p.rhs_idx, **kw)
         h.green_columns(out)
@@ -662,6 +666,7 @@ def main():
                      "hbm_gbs_from_counters": None if traffic is None else
                      achieved * traffic / traffic_alg},
         "launch_shape": {"tile": reps[-1]["tile"], "zchunk": reps[-1]["zchunk"],
+                         "zchunk_mu": reps[-1]["zchunk_mu"],
                          "shift_chunk": reps[-1]["shift_chunk"],
                          "cache_mode": reps[-1]["cache_mode"],
                          "autotuned": not a.fixed_shape},

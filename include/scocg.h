@@ -148,12 +148,19 @@ typedef struct {
                             in the last-level cache for the next mu pass); 2 both ordinary;
                             SCOCG_AUTO: autotuned with the launch shape.  Results do not
                             depend on it */
+    int32_t zchunk_mu;   /* z planes per workgroup of the mu pass (0 -> the same as zchunk;
+                            SCOCG_AUTO: autotuned after the r_{n+1} pass's shape).  The mu
+                            pass fits two workgroups per CU and needs only the forward
+                            neighbours, so longer chunks can pay there; the partial sums of
+                            (r_n, (z_s - H) r_n) are then grouped differently, which changes
+                            their rounding (and possibly the iteration count) only */
 } scocg_solve_opts;
 
-/* Autotuning: any of tile, zchunk, shift_chunk = SCOCG_AUTO makes scocg_solve time
-   short trial runs (16 seed iterations from the initial state of this very problem)
-   of each candidate launch shape -- the 4 tile shapes x up to 8 z-chunk lengths around
-   the default, then 3 shift chunks, then 3 cache policies -- before the solve proper,
+/* Autotuning: any of tile, zchunk, zchunk_mu, shift_chunk, cache_mode = SCOCG_AUTO makes
+   scocg_solve time short trial runs (16 seed iterations from the initial state of this
+   very problem) of each candidate launch shape -- the 4 tile shapes x up to 8 z-chunk
+   lengths around the default, then up to 6 z-chunk lengths of the mu pass, then 3 shift
+   chunks, then 3 cache policies -- before the solve proper,
    keep the fastest, and
    cache it in the handle for this (column blocks, energies, rows) shape; later solves
    of that shape reuse it.  Trials run outside the timed region (scocg_report.tune_ms
@@ -162,7 +169,7 @@ typedef struct {
    shape tuned by scocg_solve is also appended to it as one JSON line, e.g.
      {"arch": "gfx950", "precision": "fp64", "grid": [48, 48, 96], "nf": 4, "atoms": 40,
       "block_width": 8, "blocks": 8, "energies": 128, "rows": 64, "tile": 1,
-      "zchunk": 18, "shift_chunk": 16, "cache_mode": 0}
+      "zchunk": 18, "shift_chunk": 16, "cache_mode": 0, "zchunk_mu": 32}
    (on one line), and a solve whose handle has no entry for its shape takes the last
    matching record of the file instead of running the trials (scocg_report.tuned = 0).
    Only lines in the exact form written here are read; records with values outside
@@ -202,6 +209,7 @@ typedef struct {
     int32_t tuned;       /* out: 1 if this call ran the autotuning trials */
     double tune_ms;      /* out: device time of the autotuning trials */
     int32_t cache_mode_used; /* out: cache policy of the r_{n+1} pass (scocg_solve_opts) */
+    int32_t zchunk_mu_used;  /* out: z planes per workgroup of the mu pass */
 } scocg_report;
 
 /*
@@ -243,7 +251,8 @@ typedef struct {
  *             chunk serve the whole batch: SCOCG_AUTO for tile or shift_chunk times
  *             16-iteration trials of the whole batch per candidate before the solve
  *             (scocg_report.tune_ms, every call); each region keeps the z-chunk of its
- *             own plan (zchunk = 0 or SCOCG_AUTO) or the explicit one.
+ *             own plan (zchunk = 0 or SCOCG_AUTO) or the explicit one, and its mu pass
+ *             that z-chunk unless zchunk_mu is explicit (SCOCG_AUTO counts as 0 here).
  *   reps      [n] or NULL: per-region reports (solve_ms is the whole batch's device
  *             time; kernel_ms/kernel_launches are the shared launches).
  *   region_ms [n] or NULL: device ms from the start of the batch to the host poll at

@@ -191,6 +191,7 @@ struct scocg_ctx {
     StencilGrid g{};
     int kch = 4;  // energies per workgroup of k_shift
     int cache_mode = 0;  // cache policy of the r_{n+1} pass (StencilArgs::cache_mode)
+    int zc_mu = 0;       // z planes per workgroup of the mu pass (0: the same as g.zc)
     bool full = false;
     DevBuf r0, r1, z, cols, sh, coef, list, cnt, k5cnt, blk_active, blk_iter, rhs, srow, x, p,
         dc, qa, part0, part1;
@@ -201,7 +202,8 @@ struct scocg_ctx {
   };
   std::unique_ptr<Solve> last;
   // autotuned launch shapes per (B, column blocks, energies, rows): {tile, zchunk, kch}
-  std::map<std::array<int64_t, 4>, std::array<int32_t, 4>> tuned;
+  // {tile, zchunk, shift chunk, cache mode, mu-pass zchunk (0: the same as zchunk)}
+  std::map<std::array<int64_t, 4>, std::array<int32_t, 5>> tuned;
 };
 
 namespace {
@@ -314,12 +316,13 @@ std::string tune_key_text(const TuneKey& k) {
   return buf;
 }
 
-bool tune_record_valid(const std::array<int32_t, 4>& v, int nz) {
+bool tune_record_valid(const std::array<int32_t, 5>& v, int nz) {
   return v[0] >= 1 && v[0] <= 4 && v[1] >= 1 && v[1] <= nz &&
-         (v[2] == 1 || v[2] == 4 || v[2] == 16) && v[3] >= 0 && v[3] <= 2;
+         (v[2] == 1 || v[2] == 4 || v[2] == 16) && v[3] >= 0 && v[3] <= 2 && v[4] >= 0 &&
+         v[4] <= nz;
 }
 
-bool tune_cache_lookup(const char* path, const TuneKey& k, std::array<int32_t, 4>* out) {
+bool tune_cache_lookup(const char* path, const TuneKey& k, std::array<int32_t, 5>* out) {
   FILE* f = fopen(path, "r");
   if (!f) return false;
   const std::string key = tune_key_text(k);
@@ -327,11 +330,12 @@ bool tune_cache_lookup(const char* path, const TuneKey& k, std::array<int32_t, 4
   char line[1024];
   while (fgets(line, sizeof line, f)) {
     if (strncmp(line, key.c_str(), key.size()) != 0) continue;
-    std::array<int32_t, 4> v{};
+    std::array<int32_t, 5> v{};
     char tail = 0;
     if (sscanf(line + key.size(),
-               "\"tile\": %d, \"zchunk\": %d, \"shift_chunk\": %d, \"cache_mode\": %d%c", &v[0],
-               &v[1], &v[2], &v[3], &tail) == 5 &&
+               "\"tile\": %d, \"zchunk\": %d, \"shift_chunk\": %d, \"cache_mode\": %d, "
+               "\"zchunk_mu\": %d%c",
+               &v[0], &v[1], &v[2], &v[3], &v[4], &tail) == 6 &&
         tail == '}' && tune_record_valid(v, k.nz)) {
       *out = v;
       found = true;
@@ -341,10 +345,12 @@ bool tune_cache_lookup(const char* path, const TuneKey& k, std::array<int32_t, 4
   return found;
 }
 
-void tune_cache_append(const char* path, const TuneKey& k, const std::array<int32_t, 4>& v) {
-  char buf[128];
-  snprintf(buf, sizeof buf, "\"tile\": %d, \"zchunk\": %d, \"shift_chunk\": %d, \"cache_mode\": %d}\n",
-           v[0], v[1], v[2], v[3]);
+void tune_cache_append(const char* path, const TuneKey& k, const std::array<int32_t, 5>& v) {
+  char buf[160];
+  snprintf(buf, sizeof buf,
+           "\"tile\": %d, \"zchunk\": %d, \"shift_chunk\": %d, \"cache_mode\": %d, "
+           "\"zchunk_mu\": %d}\n",
+           v[0], v[1], v[2], v[3], v[4]);
   const std::string line = tune_key_text(k) + buf;
   const int fd = open(path, O_WRONLY | O_APPEND | O_CREAT, 0644);
   if (fd < 0) {
@@ -657,6 +663,7 @@ struct Solver {
     S.nwg = S.g.nwg;
     S.kch = o.shift_chunk > 0 ? o.shift_chunk : 4;
     S.cache_mode = o.cache_mode > 0 ? o.cache_mode : 0;
+    S.zc_mu = o.zchunk_mu > 0 ? o.zchunk_mu : 0;
     const size_t vec = (size_t)nb * bstride() * sizeof(cT);
     S.r0.alloc(vec);
     S.r1.alloc(vec);
@@ -675,7 +682,7 @@ struct Solver {
     S.p.alloc(xp * sizeof(cT));
     S.dc.alloc((size_t)std::max(h.n_atoms, 1) * nb * 4 * B * sizeof(cT));
     S.qa.alloc((size_t)std::max(h.n_atoms, 1) * nb * B * sizeof(double2));
-    S.part0.alloc((size_t)nb * S.nwg * B * sizeof(double2));
+    S.part0.alloc((size_t)nb * std::max(S.nwg, mu_grid().nwg) * B * sizeof(double2));
     S.part1.alloc((size_t)nb * S.nwg * B * sizeof(double));
     if (!S.h_flags) HIPCHK(hipHostMalloc((void**)&S.h_flags, sizeof(int32_t) * 65536));
   }
@@ -738,11 +745,28 @@ struct Solver {
 
   // switch the stencil launch shape, growing the partial-sum buffers if needed
   void set_grid(const StencilGrid& g) {
-    const size_t need = (size_t)S.nb * g.nwg * B;
-    if (S.part0.bytes < need * sizeof(double2)) S.part0.alloc(need * sizeof(double2));
-    if (S.part1.bytes < need * sizeof(double)) S.part1.alloc(need * sizeof(double));
     S.g = g;
     S.nwg = g.nwg;
+    fit_partials();
+  }
+
+  // launch shape of the mu pass: the r_{n+1} pass's tile with its own z-chunk
+  StencilGrid mu_grid() const {
+    return S.zc_mu > 0 && S.zc_mu != S.g.zc ? plan(S.nb, S.g.variant, S.zc_mu) : S.g;
+  }
+
+  void set_mu_zchunk(int zc) {
+    S.zc_mu = zc;
+    fit_partials();
+  }
+
+  // partial-sum buffers for both passes' workgroup counts
+  void fit_partials() {
+    const size_t need = (size_t)S.nb * S.g.nwg * B;
+    const size_t need_mu = (size_t)S.nb * mu_grid().nwg * B;
+    const size_t n0 = std::max(need, need_mu);
+    if (S.part0.bytes < n0 * sizeof(double2)) S.part0.alloc(n0 * sizeof(double2));
+    if (S.part1.bytes < need * sizeof(double)) S.part1.alloc(need * sizeof(double));
   }
 
   // Device time per seed iteration of `iters` iterations from the initial state
@@ -765,7 +789,7 @@ struct Solver {
   // Autotuning: time each candidate stencil shape (tile x z-chunk), then each shift
   // chunk, on this problem; keep the fastest.  Returns the device time spent.
   double tune(const double2* zk, int seed0, const scocg_solve_opts& o, bool want_tile,
-              bool want_zc, bool want_kch, bool want_cache) {
+              bool want_zc, bool want_kch, bool want_cache, bool want_zc_mu) {
     constexpr int kIters = 16;
     Event a, b;
     HIPCHK(hipEventRecord(a, h.stream));
@@ -800,6 +824,29 @@ struct Solver {
         }
       }
       set_grid(bg);
+    }
+    if (want_zc_mu) {
+      // the mu pass runs two workgroups per CU and reads only a one-sided halo: longer
+      // chunks (fewer queue refills) may pay there while the r_{n+1} pass keeps its own
+      const int zc = S.g.zc;
+      std::vector<int> zcs = {0};
+      for (int c : {zc * 4 / 3, zc * 3 / 2, zc * 2, zc * 3, h.nz})
+        if (c > zc && c <= h.nz) zcs.push_back(c);
+      std::sort(zcs.begin() + 1, zcs.end());
+      zcs.erase(std::unique(zcs.begin() + 1, zcs.end()), zcs.end());
+      double best = INFINITY;
+      int bz = 0;
+      for (int c : zcs) {
+        set_mu_zchunk(c);
+        const double us = trial(zk, seed0, o, kIters);
+        if (trace_on())
+          fprintf(stderr, "[scocg] tune mu zchunk %d: %.1f us/iteration\n", mu_grid().zc, us);
+        if (us < best) {
+          best = us;
+          bz = c;
+        }
+      }
+      set_mu_zchunk(bz);
     }
     if (want_kch) {
       double best = INFINITY;
@@ -1011,27 +1058,29 @@ struct Solver {
   double autotune(const scocg_solve_opts& o, int* tuned_now) {
     *tuned_now = 0;
     const bool auto_tile = o.tile == SCOCG_AUTO, auto_zc = o.zchunk == SCOCG_AUTO,
-               auto_kch = o.shift_chunk == SCOCG_AUTO, auto_cache = o.cache_mode == SCOCG_AUTO;
-    if (!(auto_tile || auto_zc || auto_kch || auto_cache)) return 0.0;
+               auto_kch = o.shift_chunk == SCOCG_AUTO, auto_cache = o.cache_mode == SCOCG_AUTO,
+               auto_zc_mu = o.zchunk_mu == SCOCG_AUTO;
+    if (!(auto_tile || auto_zc || auto_kch || auto_cache || auto_zc_mu)) return 0.0;
     const std::array<int64_t, 4> key{B, S.nb, S.K, S.nS};
     auto it = h.tuned.find(key);
     const char* file = getenv("SCOCG_TUNE_CACHE");
     const bool use_file = file && *file;
     const TuneKey tk{h.arch, h.precision, h.nx, h.ny, h.nz, h.nf, h.n_atoms, B, S.nb, S.K, S.nS};
     if (it == h.tuned.end() && use_file) {
-      std::array<int32_t, 4> rec{};
+      std::array<int32_t, 5> rec{};
       if (tune_cache_lookup(file, tk, &rec)) it = h.tuned.emplace(key, rec).first;
     }
     if (it != h.tuned.end()) {
       set_grid(plan(S.nb, auto_tile ? it->second[0] : o.tile, auto_zc ? it->second[1] : o.zchunk));
       if (auto_kch) S.kch = it->second[2];
       if (auto_cache) S.cache_mode = it->second[3];
+      if (auto_zc_mu) set_mu_zchunk(it->second[4]);
       return 0.0;
     }
-    const double ms =
-        tune(zk.as<double2>(), seed0, o, auto_tile, auto_zc, auto_kch, auto_cache);
+    const double ms = tune(zk.as<double2>(), seed0, o, auto_tile, auto_zc, auto_kch,
+                           auto_cache, auto_zc_mu);
     *tuned_now = 1;
-    h.tuned[key] = {S.g.variant, S.g.zc, S.kch, S.cache_mode};
+    h.tuned[key] = {S.g.variant, S.g.zc, S.kch, S.cache_mode, S.zc_mu};
     if (use_file) tune_cache_append(file, tk, h.tuned[key]);
     return ms;
   }
@@ -1121,6 +1170,7 @@ struct Solver {
       rep->zchunk_used = S.g.zc;
       rep->shift_chunk_used = S.kch;
       rep->cache_mode_used = S.cache_mode;
+      rep->zchunk_mu_used = mu_grid().zc;
       rep->tuned = tuned_now;
       rep->tune_ms = tune_ms;
     }
@@ -1190,7 +1240,8 @@ struct Batch {
       int32_t* act = S.blk_active.template as<int32_t>();
       double2* part0 = S.part0.template as<double2>();
       double* part1 = S.part1.template as<double>();
-      StencilArgs<T> m = p->stencil_args(MODE_MU, S.g, S.nb, cols, act, part0, nullptr,
+      const StencilGrid gm = p->mu_grid();
+      StencilArgs<T> m = p->stencil_args(MODE_MU, gm, S.nb, cols, act, part0, nullptr,
                                          S.dc.template as<cT>(), S.qa.template as<double2>());
       // x, p update of iteration n inside the mu launch of iteration n + 1
       m.shift = p->shift_args(SV::tile_cfg(h.nf == 4 ? variant : 1).nt, kch);
@@ -1204,12 +1255,12 @@ struct Batch {
         q->bufs[1] = to_g(b1);
       }
       mu.push_back(m);
-      omu.push_back(omu.back() + SV::stencil_wgs(m, S.g));
+      omu.push_back(omu.back() + SV::stencil_wgs(m, gm));
       up.push_back(u);
       oup.push_back(oup.back() + SV::stencil_wgs(u, S.g));
       AlphaArgs aa{};
       aa.part = to_g(part0);
-      aa.nwg = S.nwg;
+      aa.nwg = gm.nwg;
       aa.qa = to_g(S.qa.template as<double2>());
       aa.n_atoms = h.n_atoms;
       aa.cols = to_g(cols);
@@ -1765,6 +1816,7 @@ scocg_solve_opts check_opts(const scocg_solve_opts* opts) {
   require(o.timing >= 0 && o.timing <= 2, "timing must be 0, 1 or 2");
   require(o.tile >= SCOCG_AUTO && o.tile <= 4, "tile must be SCOCG_AUTO or 0..4");
   require(o.zchunk >= SCOCG_AUTO, "zchunk must be SCOCG_AUTO or >= 0");
+  require(o.zchunk_mu >= SCOCG_AUTO, "zchunk_mu must be SCOCG_AUTO or >= 0");
   require(o.cache_mode >= SCOCG_AUTO && o.cache_mode <= 2,
           "cache_mode must be SCOCG_AUTO, 0, 1 or 2");
   require(o.shift_chunk == SCOCG_AUTO || o.shift_chunk == 0 || o.shift_chunk == 1 ||
@@ -1876,6 +1928,7 @@ int run_batch(int n, const scocg_handle* hs, const scocg_problem* pr, scocg_solv
   if (o.zchunk == SCOCG_AUTO) o.zchunk = 0;
   if (o.shift_chunk == SCOCG_AUTO) o.shift_chunk = 0;
   if (o.cache_mode == SCOCG_AUTO) o.cache_mode = 0;
+  if (o.zchunk_mu == SCOCG_AUTO) o.zchunk_mu = 0;  // each region's mu pass follows its zchunk
   std::vector<std::unique_ptr<Solver<T, B>>> sv;
   std::vector<Solver<T, B>*> ptr;
   for (int i = 0; i < n; ++i) {

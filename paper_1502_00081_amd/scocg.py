@@ -41,7 +41,7 @@ class SolveOpts(C.Structure):
                 ("tile", C.c_int32), ("zchunk", C.c_int32), ("shift_chunk", C.c_int32),
                 ("conventional", C.c_int32), ("aux_seed", C.c_int32),
                 ("seed_z", C.c_double * 2), ("symmetric", C.c_int32),
-                ("cache_mode", C.c_int32)]
+                ("cache_mode", C.c_int32), ("zchunk_mu", C.c_int32)]
 
 
 class Report(C.Structure):
@@ -52,7 +52,7 @@ class Report(C.Structure):
                 ("kernel_ms", C.c_double * 6), ("kernel_launches", C.c_int64 * 6),
                 ("tile_used", C.c_int32), ("zchunk_used", C.c_int32),
                 ("shift_chunk_used", C.c_int32), ("tuned", C.c_int32), ("tune_ms", C.c_double),
-                ("cache_mode_used", C.c_int32)]
+                ("cache_mode_used", C.c_int32), ("zchunk_mu_used", C.c_int32)]
 
 class Problem(C.Structure):
     _fields_ = [("K", C.c_int32), ("z", C.c_void_p), ("R", C.c_int32), ("rhs_idx", C.c_void_p),
@@ -139,7 +139,7 @@ def _dev_ptr(t):
 
 def _opts(tol, max_iter, init_seed, seed_switch, full, refine, poll_every, use_graph, timing,
           tile, zchunk, shift_chunk, conventional=False, seed_z=None, symmetric=False,
-          cache_mode=0):
+          cache_mode=0, zchunk_mu=0):
     o = SolveOpts(float(tol), int(max_iter), int(init_seed), int(bool(seed_switch)),
                   int(bool(full)), int(refine), int(poll_every), int(bool(use_graph)),
                   int(timing), int(tile), int(zchunk), int(shift_chunk),
@@ -149,6 +149,7 @@ def _opts(tol, max_iter, init_seed, seed_switch, full, refine, poll_every, use_g
         o.seed_z[0], o.seed_z[1] = float(np.real(seed_z)), float(np.imag(seed_z))
     o.symmetric = int(bool(symmetric))
     o.cache_mode = int(cache_mode)
+    o.zchunk_mu = int(zchunk_mu)
     return o
 
 
@@ -168,7 +169,8 @@ def _report_dict(rep, arrays):
                 kernel_ms=dict(zip(KERNEL_FAMILIES, list(rep.kernel_ms))),
                 kernel_launches=dict(zip(KERNEL_FAMILIES, list(rep.kernel_launches))),
                 tile=rep.tile_used, zchunk=rep.zchunk_used, shift_chunk=rep.shift_chunk_used,
-                tuned=bool(rep.tuned), tune_ms=rep.tune_ms, cache_mode=rep.cache_mode_used)
+                tuned=bool(rep.tuned), tune_ms=rep.tune_ms, cache_mode=rep.cache_mode_used,
+                zchunk_mu=rep.zchunk_mu_used)
 
 
 class Handle:
@@ -183,7 +185,7 @@ class Handle:
     def solve(self, z, rhs_idx, s_idx=None, tol=1e-10, max_iter=100000, init_seed=-1,
               seed_switch=True, full=False, refine=0, poll_every=0, use_graph=False, timing=0,
               tile=0, zchunk=0, shift_chunk=0, conventional=False, seed_z=None,
-              symmetric=False, cache_mode=0):
+              symmetric=False, cache_mode=0, zchunk_mu=0):
         """scocg_solve; returns (rc, report dict with [K, R] arrays).  conventional=True runs
         every (energy, column) pair as its own recurrence (the comparison sweep).  seed_z (a
         complex energy, not necessarily one of z) starts the seed recurrence there.
@@ -194,7 +196,8 @@ class Handle:
         rhs = _c(rhs_idx, np.int64)
         sp = None if s_idx is None else _c(s_idx, np.int64)
         o = _opts(tol, max_iter, init_seed, seed_switch, full, refine, poll_every, use_graph,
-                  timing, tile, zchunk, shift_chunk, conventional, seed_z, symmetric, cache_mode)
+                  timing, tile, zchunk, shift_chunk, conventional, seed_z, symmetric, cache_mode,
+                  zchunk_mu)
         rep, arrays = _new_report(z.size, rhs.size)
         rc = lib.scocg_solve(self._h, z.size, z.ctypes.data, rhs.size, rhs.ctypes.data,
                              0 if sp is None else sp.size,
@@ -294,7 +297,7 @@ def create_from_problem(p, precision=FP64, stream=None) -> Handle:
 
 def batch_solve(handles, problems, tol=1e-10, max_iter=100000, seed_switch=True, full=False,
                 refine=0, poll_every=0, use_graph=False, timing=0, tile=0, zchunk=0,
-                shift_chunk=0, symmetric=False, cache_mode=0):
+                shift_chunk=0, symmetric=False, cache_mode=0, zchunk_mu=0):
     """scocg_batch_solve over regions; problems: [(z, rhs_idx) or (z, rhs_idx, s_idx)].
     Returns (rc, [report dict per region], region_ms [n])."""
     lib = load()
@@ -315,7 +318,8 @@ def batch_solve(handles, problems, tol=1e-10, max_iter=100000, seed_switch=True,
         handles[i].last = (z.size, rhs.size, nrows)
     hs = (C.c_void_p * n)(*[h._h.value for h in handles])
     o = _opts(tol, max_iter, -1, seed_switch, full, refine, poll_every, use_graph, timing, tile,
-              zchunk, shift_chunk, symmetric=symmetric, cache_mode=cache_mode)
+              zchunk, shift_chunk, symmetric=symmetric, cache_mode=cache_mode,
+              zchunk_mu=zchunk_mu)
     region_ms = np.zeros(n)
     rc = lib.scocg_batch_solve(n, hs, probs, C.byref(o), reps, region_ms.ctypes.data)
     _check(rc)

@@ -231,6 +231,38 @@ def test_autotuned_launch_shape_is_cached_and_exact(dev):
     assert np.abs(G1 - G4).max() <= 4e-10 / eta
 
 
+def test_mu_pass_with_its_own_zchunk(dev):
+    """A mu pass with longer z-chunks than the r_{n+1} pass (zchunk_mu) regroups only the
+    partial sums of (r_n, (z_s - H) r_n): the solve is bitwise repeatable, reports the
+    mu pass's chunk, and agrees with the shared-chunk solve and the oracle within the
+    parity bound; SCOCG_AUTO tunes it."""
+    p = W.tiny_fp64()
+    h = scocg.create_from_problem(p, precision=scocg.FP64)
+    rc, r0 = h.solve(p.z, p.rhs_idx, tol=1e-10, tile=1, zchunk=6, shift_chunk=4)
+    G0 = h.green_columns()
+    assert rc == scocg.OK and r0["zchunk_mu"] == 6
+    rc, r1 = h.solve(p.z, p.rhs_idx, tol=1e-10, tile=1, zchunk=6, shift_chunk=4, zchunk_mu=24)
+    G1 = h.green_columns()
+    assert rc == scocg.OK and r1["zchunk"] == 6 and r1["zchunk_mu"] == 24
+    assert (r1["status"] == scocg.PAIR_CONVERGED).all()
+    rc, r2 = h.solve(p.z, p.rhs_idx, tol=1e-10, tile=1, zchunk=6, shift_chunk=4, zchunk_mu=24)
+    assert np.array_equal(h.green_columns(), G1)
+    A = scocg.AUTO
+    rc, ra = h.solve(p.z, p.rhs_idx, tol=1e-10, tile=1, zchunk=6, shift_chunk=4, zchunk_mu=A)
+    assert rc == scocg.OK and ra["tuned"] and ra["zchunk_mu"] in (6, 8, 9, 12, 18, 24)
+    with pytest.raises(scocg.ScocgError):
+        h.solve(p.z, p.rhs_idx, tol=1e-10, zchunk_mu=-2)
+    h.destroy()
+    eta = p.z.imag.min()
+    assert np.abs(G1 - G0).max() <= 4e-10 / eta
+    ref, it, st, _ = oracle.cocg_unit_columns(p, p.z, p.rhs_idx, p.rhs_idx,
+                                              [(k, j) for k in (0, 7, 15) for j in (0, 5)],
+                                              tol=1e-10, max_iter=20000)
+    assert (st == oracle.CONVERGED).all()
+    for s, (k, j) in enumerate([(k, j) for k in (0, 7, 15) for j in (0, 5)]):
+        assert np.linalg.norm(G1[k, j] - ref[s]) <= 2.2e-10 / eta
+
+
 def test_green_function_symmetry_and_invariants(dev):
     """S = RHS set = the whole iz=0 plane: G(z_0, z_0) is complex symmetric,
     Im G_ii < 0 and |G_ij| <= 1/eta."""
