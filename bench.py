@@ -357,7 +357,33 @@ def obm_measure(a, steps, warmup, wide=False):
             phases.append(ph)
         say(f"{'warmup' if i < warmup else 'step'} {i}: solve {1e3 * (t1 - t0):.1f} ms "
             f"({rep['seed_iters']} iterations), matching {1e3 * (t2 - t1):.1f} ms")
+    # the mu pass with the x, p update near full activity: a solve capped at 256 seed
+    # iterations, every launch timed with HIP events (outside the timed steps)
+    cap = 256
+    rc, rc_rep = h.solve(p.z, p.rhs_idx, **dict(kw, max_iter=cap, timing=1))
     h.destroy()
+    assert rc in (scocg.OK, scocg.NOT_ALL_CONVERGED), rc
+    # bytes over the capped solve: r_n read per (column, iteration) of each active block;
+    # x and p (complex128) read and written per kept row of each pair's updates (pair
+    # (k, j) is updated in iterations 0 .. f-1, the last one outside the mu launches;
+    # symmetric rows: the block of column j keeps rows i >= 8 (j // 8))
+    B = rc_rep["block_width"]
+    kept = np.array([D - B * (j // B) if not a.no_symmetric else D for j in range(D)])
+    upd = np.minimum(rc_rep["iters"], cap - 1)  # [K, D]
+    xp_total = float((upd * kept[None, :]).sum()) * 64.0
+    st_total = float(rc_rep["block_iters"]) * B * p.n * 16.0
+    lm, tm = rc_rep["kernel_launches"]["mu"], rc_rep["kernel_ms"]["mu"]
+    mu_full = {"iterations": cap,
+               "pairs_still_running": int((rc_rep["status"] == scocg.PAIR_MAXITER).sum()),
+               "pairs": int(K * D), "avg_launch_us": tm * 1e3 / lm,
+               "bytes_per_launch": (xp_total + st_total) / lm,
+               "xp_bytes_per_launch": xp_total / lm,
+               "gbs": (xp_total + st_total) / (tm * 1e-3) / 1e9,
+               "frac_of_8tbs": (xp_total + st_total) / (tm * 1e-3) / 8e12}
+    mu_us = mu_full["avg_launch_us"]
+    say(f"mu pass with the x, p update, {cap} capped iterations: {mu_us:.1f} us per launch, "
+        f"{mu_full['gbs']:.0f} GB/s ({mu_full['pairs_still_running']} of {K * D} pairs "
+        f"still running)")
     ts, to = float(np.mean(solve_s)), float(np.mean(obm_s))
     ph = np.mean(phases, axis=0)
     ncol = n + D
@@ -388,6 +414,7 @@ def obm_measure(a, steps, warmup, wide=False):
                      "unit": "TFLOP/s", "frac": upd_flops / (ph[2] * 1e-3) / 1e12 / 78.6,
                      "traffic": None, "bytes_per_s": upd_bytes / (ph[2] * 1e-3) / 1e9},
         "cpu_baseline": cpu,
+        "mu_pass_capped": mu_full,
         "T": [round(float(x), 6) for x in T.real], "dos": [round(float(x), 6) for x in dos]}
 
 

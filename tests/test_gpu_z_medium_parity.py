@@ -3,7 +3,8 @@
 top of the energy window, where the slowest pairs and every seed switch are.
 
 GPU solves through the C ABI, once per module:
-  * the benchmarked launch (projected storage, every energy and column, tol 1e-8):
+  * the benchmarked launch (projected storage, every energy and column, tol 1e-8,
+    autotuned launch shape, graph replay):
     size-independent properties on every pair, and its rows of the sampled pairs;
   * full storage, 5 energies (0, 40, 96, 120, 127) x 8 columns (4 on each boundary
     plane), tol 1e-8: every pair's true residual ||e_j - (z_k - H) x||, evaluated with
@@ -66,9 +67,14 @@ def medium():
     h = scocg.create_from_problem(base, precision=scocg.FP64)
     try:
         t0 = time.perf_counter()
-        rc, rep = h.solve(base.z, base.rhs_idx, tol=1e-8, use_graph=True, max_iter=40000)
+        # the benchmarked launch: autotuned shape, graph replay
+        A = scocg.AUTO
+        rc, rep = h.solve(base.z, base.rhs_idx, tol=1e-8, use_graph=True, max_iter=40000,
+                          tile=A, zchunk=A, zchunk_mu=A, shift_chunk=A, cache_mode=A)
         say(f"medium projected: rc={rc}, {rep['seed_iters']} seed iterations, "
-            f"{rep['n_switches']} switches, {time.perf_counter() - t0:.1f} s")
+            f"{rep['n_switches']} switches, shape tile {rep['tile']} zchunk {rep['zchunk']} "
+            f"(mu {rep['zchunk_mu']}) shift chunk {rep['shift_chunk']} cache mode "
+            f"{rep['cache_mode']}, {time.perf_counter() - t0:.1f} s")
         out["proj"] = (rc, rep, h.green_columns())  # [K, R, R]
     finally:
         h.destroy()
