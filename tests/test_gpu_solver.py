@@ -500,6 +500,28 @@ def test_batch_of_uneven_regions_matches_single_solves(dev, prec):
         h.destroy()
 
 
+def test_batch_with_its_own_mu_zchunk_matches_single_solves(dev):
+    """An explicit mu-pass z-chunk in a batch gives each region's mu pass that chunk:
+    the batch equals the single solves with the same options bit for bit."""
+    regs = [small(16, 16, 20, 4, True, K=6, nb=3, nt=3, seed=5), W.tiny_fp64()]
+    kw = dict(tol=1e-10, tile=1, zchunk=6, shift_chunk=4, zchunk_mu=12)
+    stream = torch.cuda.Stream()
+    hs = [scocg.create_from_problem(p, precision=scocg.FP64, stream=stream) for p in regs]
+    single = []
+    for h, p in zip(hs, regs):
+        rc, rep = h.solve(p.z, p.rhs_idx, **kw)
+        assert rc == scocg.OK and rep["zchunk_mu"] == 12
+        single.append((rep, h.green_columns()))
+    rc, reps, _ = scocg.batch_solve(hs, [(p.z, p.rhs_idx) for p in regs], use_graph=True, **kw)
+    assert rc == scocg.OK
+    for i, h in enumerate(hs):
+        assert reps[i]["zchunk_mu"] == 12
+        assert np.array_equal(h.green_columns(), single[i][1]), i
+        assert np.array_equal(reps[i]["iters"], single[i][0]["iters"]), i
+    for h in hs:
+        h.destroy()
+
+
 def test_batch_rejects_mismatched_handles(dev):
     p = small(16, 16, 10, 4, False, K=4, nb=2, nt=2, seed=3)
     s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
