@@ -357,22 +357,23 @@ def obm_measure(a, steps, warmup, wide=False):
             phases.append(ph)
         say(f"{'warmup' if i < warmup else 'step'} {i}: solve {1e3 * (t1 - t0):.1f} ms "
             f"({rep['seed_iters']} iterations), matching {1e3 * (t2 - t1):.1f} ms")
-    # the mu pass with the x, p update near full activity: a solve capped at 256 seed
+    # the mu pass with the x, p update near full activity: a solve capped at 270 seed
     # iterations, every launch timed with HIP events (outside the timed steps)
-    cap = 256
+    cap = 270  # a whole number of 18-iteration poll chunks
     rc, rc_rep = h.solve(p.z, p.rhs_idx, **dict(kw, max_iter=cap, timing=1))
     h.destroy()
     assert rc in (scocg.OK, scocg.NOT_ALL_CONVERGED), rc
     # bytes over the capped solve: r_n read per (column, iteration) of each active block;
     # x and p (complex128) read and written per kept row of each pair's updates (pair
     # (k, j) is updated in iterations 0 .. f-1, the last one outside the mu launches;
-    # symmetric rows: the block of column j keeps rows i >= 8 (j // 8))
+    # symmetric rows: the block of column j keeps rows i >= 8 (j // 8)); the update of
+    # iteration n runs in the mu launch of n + 2
     B = rc_rep["block_width"]
     kept = np.array([D - B * (j // B) if not a.no_symmetric else D for j in range(D)])
-    upd = np.minimum(rc_rep["iters"], cap - 1)  # [K, D]
+    lm, tm = rc_rep["kernel_launches"]["mu"], rc_rep["kernel_ms"]["mu"]
+    upd = np.minimum(rc_rep["iters"], lm - 2)  # [K, D]
     xp_total = float((upd * kept[None, :]).sum()) * 64.0
     st_total = float(rc_rep["block_iters"]) * B * p.n * 16.0
-    lm, tm = rc_rep["kernel_launches"]["mu"], rc_rep["kernel_ms"]["mu"]
     mu_full = {"iterations": cap,
                "pairs_still_running": int((rc_rep["status"] == scocg.PAIR_MAXITER).sum()),
                "pairs": int(K * D), "avg_launch_us": tm * 1e3 / lm,
@@ -427,10 +428,12 @@ def _capped_rates(p, rep, iters, prec_fp64):
     8 TB/s of the two stencil passes of a capped solve (S = the right-hand-side points)
     of `iters` iterations.
       r_{n+1} pass: 3 N s_v per (column, iteration): read r_n, r_{n-1}, write r_{n+1};
-      mu pass: N s_v per (column, iteration) read, plus the x, p update of the previous
-        iteration it carries: per (energy, row, column) x read and written (2 x 16 B) and
-        p read and written (2 x 16 B FP64, 2 x 8 B complex64); the mu launch of the first
-        iteration carries none, the update of the last runs in a separate flush."""
+      mu pass: N s_v per (column, iteration) read, plus the x, p update it carries (that
+        of iteration n - 2 in the launch of n): per (energy, row, column) x read and
+        written (2 x 16 B) and p read and written (2 x 16 B FP64, 2 x 8 B complex64); the
+        updates of the last two iterations run in separate flushes.
+      The solve runs whole poll chunks (18 iterations): a cap that is a multiple of 18
+      leaves no idle launches in the averages."""
     sv = 16 if prec_fp64 else 8
     sp = 16 if prec_fp64 else 8
     K, R, N = p.z.size, p.rhs_idx.size, p.n
@@ -442,9 +445,9 @@ def _capped_rates(p, rep, iters, prec_fp64):
     mu = cols_it * N * sv
     nS = R  # S = the right-hand-side points
     # pair (k, j) is updated in iterations 0 .. f-1 (f: its freeze iteration, the cap for
-    # pairs still running); the update of iteration n runs in the mu launch of n + 1, the
-    # last iteration's in the flush
-    upd_in_mu = np.minimum(rep["iters"], iters - 1).sum()
+    # pairs still running); the update of iteration n runs in the mu launch of n + 2, those
+    # of the last two launched iterations in the flushes
+    upd_in_mu = np.minimum(rep["iters"], lm - 2).sum()
     xp = int(upd_in_mu) * nS * (32 + 2 * sp)
     out = {}
     for name, by, ms, n in (("r_next_pass", upd, tu, lu), ("mu_pass_with_xp_update", mu + xp, tm, lm)):
@@ -456,7 +459,7 @@ def _capped_rates(p, rep, iters, prec_fp64):
     return out
 
 
-def peapod_large_measure(a, capped_iters=256):
+def peapod_large_measure(a, capped_iters=270):
     """The peapod-shaped configuration (64x64x160 grid, 400 atoms on a 12.85 bohr cylinder
     plus 60 on a 6.614 bohr sphere, 4 projectors each; 512 energies in [-0.5, 0.5] Ha,
     eta = 5e-4; 512 + 512 boundary columns) on one GPU.

@@ -110,7 +110,8 @@ typedef struct {
                             the check); ignored for SCOCG_FP64.  With the check, a
                             SCOCG_MIXED pair is SCOCG_PAIR_CONVERGED iff its FP64 true
                             residual is <= tol */
-    int32_t poll_every;  /* seed iterations between host convergence polls; 0 -> auto */
+    int32_t poll_every;  /* seed iterations between host convergence polls, rounded up to a
+                            multiple of 6; 0 -> 18 */
     int32_t use_graph;   /* 1: replay the per-poll iterations as one captured hipGraph */
     int32_t timing;      /* 1: bracket every kernel launch with HIP events and report the
                             summed durations per kernel family (scocg_report.kernel_ms);
@@ -180,12 +181,16 @@ typedef struct {
 
 /* kernel families of one seed iteration (index into scocg_report.kernel_ms) */
 #define SCOCG_K_PROJ 0     /* (reported as 0: the projector contraction runs inside SCOCG_K_MU) */
-#define SCOCG_K_MU 1       /* stencil pass: partials of (r_n, A r_n) + projector contraction */
+#define SCOCG_K_MU 1       /* stencil pass: partials of (r_n, H r_n) + projector contraction;
+                              the same launch runs the control step of iteration n - 1 (but
+                              at the start of a poll chunk) and the x^(k), p^(k) update of
+                              iteration n - 2 */
 #define SCOCG_K_ALPHA 2    /* seed alpha_n, c_n */
 #define SCOCG_K_UPDATE 3   /* stencil pass: r_{n+1} (three-term recurrence) + dot partials */
-#define SCOCG_K_CONTROL 4  /* beta_n, pi recurrences, convergence, compaction, seed switch */
+#define SCOCG_K_CONTROL 4  /* beta_n, pi recurrences, convergence, compaction, seed switch:
+                              timed only where it runs alone, at the end of each poll chunk */
 #define SCOCG_K_SHIFT 5    /* (reported as 0: the x^(k), p^(k) update of iteration n runs in the
-                              SCOCG_K_MU launch of iteration n + 1) */
+                              SCOCG_K_MU launch of iteration n + 2) */
 #define SCOCG_K_FAMILIES 6
 
 typedef struct {

@@ -85,6 +85,9 @@ struct ColState {
   double2 alpha;       // alpha_n (set by k_alpha)
   double2 c;           // beta_{n-1} alpha_n / alpha_{n-1}
   double2 zs;          // current seed energy
+  double2 zs_mu;       // the seed energy the next mu pass uses (set by k_alpha; a seed
+                       // switch in the control step running beside that pass changes zs
+                       // only, and k_alpha corrects for the difference)
   double2 scale[2];    // stored Krylov buffer b holds r / scale[b] (lazy seed-switch rescale)
   double2 ar, ah, ap;  // r_{n+1} = ar r^st_n + ah (H r^st_n) + ap r^st_{n-1}
   double bnorm;        // ||b||
@@ -157,10 +160,10 @@ struct ShiftArgs {
   int64_t bstride;            // elements per column block
   gptr<const int32_t> srow;        // [nS] rows S (null: all N rows)
   int nS;
-  gptr<const int32_t> list;        // [2][nb][K] active shift lists (read list[par])
-  gptr<const int32_t> k5cnt;       // [nb] entries of the list this iteration
+  gptr<const int32_t> list;        // [3][nb][K] active shift lists (iteration m: m mod 3)
+  gptr<const int32_t> k5cnt;       // [2][nb] entries of iteration m's update (m mod 2)
   int K, nb;
-  gptr<const ShiftCoef> coef;      // [nb][K][B]
+  gptr<const ShiftCoef> coef;      // [2][nb][K][B] by iteration parity
   gptr<double2> x;                 // [nb][K][nS][B]
   gptr<cT> p;                      // [nb][K][nS][B]
   int gx, gy;                 // workgroups per block along rows and along the list
@@ -466,10 +469,12 @@ __global__ __launch_bounds__(WG) void k_proj(const typename cplx_of<T>::type* __
 //
 // FULL: the tile lies inside the x-y plane (no ragged points).
 //
-// MODE_MU uses r^T H r = sum_p r_p (d_p r_p + 2 sum_{axis,k>0} c_k r_{p+k}) (H
-// symmetric; every index pair (p, p+k) of the periodic or truncated axis is
-// counted once), so it needs only the forward neighbours and a one-sided halo;
-// the projector share r^T P D P^T r comes from the contraction (qa).
+// MODE_MU forms partials of r^T (z_s - H_loc) r = sum_p r_p ((z_s - d_p) r_p - 2 sum_{axis,
+// k>0} c_k r_{p+k}) (H symmetric; every index pair (p, p+k) of the periodic or truncated
+// axis is counted once), so it needs only the forward neighbours and a one-sided halo;
+// the projector share r^T P D P^T r comes from the contraction (qa).  z_s is the seed
+// energy k_alpha left for the pass (ColState::zs_mu): a control step running beside
+// the pass may switch the seed, and k_alpha then adds (z_s,new - z_s,pass) (r, r).
 template <typename T>
 __device__ __forceinline__ T fmat(T a, T b, T c);
 template <>
@@ -522,7 +527,7 @@ struct StencilWG {
   bool val[OPT];
   cT Q[OPT][W];
   cT pq[OPT], ph[HPT], pp[OPT];
-  T zr, zi;
+  T zr, zi;  // MU: the seed energy of the pass
   double2 acc0;
   double acc1;
 
@@ -580,19 +585,18 @@ struct StencilWG {
       const int g = wrapi(y0 + sy - O, ny) * nx + wrapi(x0 + sx - O, nx);
       hoff[i] = ((uint32_t)g * B + c) * ESZ;
     }
-    double2 zs = mk(0, 0);
-    if (MODE != MODE_APPLY) {
+    if (MODE == MODE_UPDATE && pl == 0) {  // read after the first plane's barrier
       const ColState& cs = a.cols[cb * B + c];
-      zs = cs.zs;
-      if (MODE == MODE_UPDATE && pl == 0) {  // read after the first plane's barrier
-        double2* sc = reinterpret_cast<double2*>(smem + COEF_OFF);
-        sc[c] = cs.ar;
-        sc[B + c] = cs.ah;
-        sc[2 * B + c] = cs.ap;
-      }
+      double2* sc = reinterpret_cast<double2*>(smem + COEF_OFF);
+      sc[c] = cs.ar;
+      sc[B + c] = cs.ah;
+      sc[2 * B + c] = cs.ap;
     }
-    zr = (T)zs.x;
-    zi = (T)zs.y;
+    if (MODE == MODE_MU) {
+      const double2 zs = a.cols[cb * B + c].zs_mu;
+      zr = (T)zs.x;
+      zi = (T)zs.y;
+    }
     acc0 = mk(0, 0);
     acc1 = 0.0;
     // odd z-chunks of the UPDATE/APPLY passes march downwards: the queue planes that
@@ -693,6 +697,7 @@ struct StencilWG {
       const cT* L = lds + iofs[m];
       if constexpr (SYM) {
         // t = (z_s - d_p) r_p - 2 sum_k c_k (r_{p+k x} + r_{p+k y} + r_{p+k z});  mu += r_p t
+        // (z_s - d_p formed per point: no cancellation between z_s (r, r) and r^T H r)
         T fr = 0, fi = 0;
 #pragma unroll
         for (int k = 1; k <= NF; ++k) {
@@ -843,6 +848,39 @@ struct StencilWG {
   }
 };
 
+// ------------------------------------------------------------------ column control
+struct ControlArgs {
+  gptr<const double2> part_rho;  // [nb][nwg][B]
+  gptr<const double> part_nu;    // [nb][nwg][B]
+  int nwg;
+  gptr<ColState> cols;
+  gptr<ShiftState> sh;           // [nb][K][B]
+  gptr<ShiftCoef> coef;          // [2][nb][K][B] by iteration parity
+  gptr<const double2> z;         // [nb][K][B] energies per column
+  int K;
+  gptr<int32_t> list;            // [3][nb][K] active shift lists, iteration n uses n mod 3
+  gptr<int32_t> cnt;             // [3][nb] their lengths
+  gptr<int32_t> k5cnt;           // [2][nb] list entries of iteration n's x, p update (n mod 2)
+  gptr<double> pim;              // [nb][K][B] |pi_{n+1}| scratch (inside the mu launch)
+  gptr<unsigned char> act;       // [nb][K][B] activity scratch (inside the mu launch)
+  gptr<int32_t> blk_active;      // [nb]
+  gptr<int32_t> blk_iter;        // [nb]
+  int nb;                   // column blocks
+  double tol;
+  int64_t max_iter;
+  int seed_switch;
+  int stall;                // > 0 (complex64 recurrences): freeze a pair whose est is
+                            // below 1e-2 and has not halved in max(stall, n/2) iterations
+  double floor_est;         // complex64 recurrences: freeze at est <= max(tol, floor_est)
+};
+
+template <int B, int CTH>
+struct CtlShared;
+template <int B, int CTH>
+__device__ __forceinline__ void control_body(const ControlArgs& a, int cb, int par, int lsel,
+                                             CtlShared<B, CTH>& sm, double* pim,
+                                             unsigned char* act);
+
 // Stencil pass kernel.  MODE_MU launches additionally carry the projector
 // contraction of r_n: the first nproj_wg workgroups (a multiple of 8, so the
 // XCD slicing of the stencil workgroups is unchanged) each contract one
@@ -853,14 +891,33 @@ template <typename T, int NF, int B, int MODE, int TX, int TY, int NT, bool FULL
 __global__ __launch_bounds__(NT)
 __attribute__((amdgpu_waves_per_eu(MODE == MODE_MU && NT == 1024 ? 8 : 4)))
 void k_stencil(const StencilArgs<T>* __restrict__ regs, const int32_t* __restrict__ off,
-               int nreg, int cur) {
+               int nreg, int cur, const ControlArgs* __restrict__ cregs,
+               const int32_t* __restrict__ coff, int nctl, int n6) {
   using SW = StencilWG<T, NF, B, MODE, TX, TY, NT, FULL>;
   using cT = typename cplx_of<T>::type;
   constexpr int PROJ_BYTES = 8 * NT * (int)sizeof(T);
   __shared__ __align__(16) char smem[SW::SMEM > PROJ_BYTES ? SW::SMEM : PROJ_BYTES];
   static_assert(PROJ_BYTES >= SHIFT_KCH_MAX * B * (int)sizeof(ShiftCoef),
                 "the shift workgroups stage their coefficients in this buffer");
+  static_assert(sizeof(CtlShared<B, NT>) <= sizeof(smem),
+                "the control workgroups keep their reductions in this buffer");
   int bid = blockIdx.x;
+  // MU launch of iteration n (n6 = n mod 6, cur = n mod 2): the first nctl workgroups
+  // (every region's column blocks, table cregs / coff) run the control step of
+  // iteration n - 1, which this pass does not depend on (its partials are independent
+  // of the seed and of the lazy scales); its [K][B] scratch is global here
+  if (MODE == MODE_MU && nctl > 0) {
+    if (bid < nctl) {
+      const int crg = region_of(coff, nreg, bid);
+      const ControlArgs ca = cregs[crg];
+      const int cb = bid - coff[crg];
+      const int64_t o = (int64_t)cb * ca.K * B;
+      control_body<B, NT>(ca, cb, cur ^ 1, (n6 + 5) % 3,
+                          *reinterpret_cast<CtlShared<B, NT>*>(smem), ca.pim + o, ca.act + o);
+      return;
+    }
+    bid -= nctl;
+  }
   const int rg = region_of(off, nreg, bid);
   // a private copy: the compiler keeps the uniform fields in scalar registers instead
   // of reloading them from the table after every global store
@@ -883,11 +940,13 @@ void k_stencil(const StencilArgs<T>* __restrict__ regs, const int32_t* __restric
     bid -= a.nproj_wg;
   }
   if (MODE == MODE_MU && a.nshift_wg > 0) {
-    // the previous iteration's x, p update (parity cur ^ 1): it reads r_n[S], which
-    // this pass only reads, and x, p, which no other workgroup touches
+    // the x, p update of iteration n - 2 (parity cur, list (n - 2) mod 3, coefficients
+    // from the control step of n - 2, which finished in the previous launch): it reads
+    // r_{n-1}[S], which stays in the other buffer until this iteration's r_{n+1} pass,
+    // and x, p, which no other workgroup touches
     if (bid < a.nshift_wg) {
       if (bid < a.shift.gx * a.shift.gy * a.shift.nb)
-        shift_body<T, B, NT>(a.shift, bid, cur ^ 1, smem);
+        shift_body<T, B, NT>(a.shift, bid, cur, (n6 + 4) % 3, smem);
       return;
     }
     bid -= a.nshift_wg;
@@ -932,7 +991,8 @@ __global__ __launch_bounds__(WG) void k_alpha(const AlphaArgs* __restrict__ regs
   const auto blk_active = ar.blk_active;
   const int tid = threadIdx.x, c = tid % B, ln = tid / B, cb = blockIdx.x - off[rg];
   if (!blk_active[cb]) return;
-  // mu^st = sum of the local stencil partials - sum over atoms of r^T P D P^T r
+  // (r^st)^T (z_pass - H) r^st = sum of the local stencil partials - sum over atoms of
+  // r^T P D P^T r, z_pass = cs.zs_mu
   double2 acc = mk(0, 0);
   for (int w = ln; w < nwg; w += PTS) acc = cadd(acc, part[((int64_t)cb * nwg + w) * B + c]);
   for (int at = ln; at < n_atoms; at += PTS) acc = csub(acc, qa[((int64_t)cb * n_atoms + at) * B + c]);
@@ -950,8 +1010,12 @@ __global__ __launch_bounds__(WG) void k_alpha(const AlphaArgs* __restrict__ regs
     return;
   }
   const double2 s_cur = cs.scale[buf_cur], s_prev = cs.scale[buf_cur ^ 1];
-  // stored r^st = r / s  =>  mu = s^2 mu^st (unconjugated bilinear form)
-  const double2 mu = cmul(cmul(s_cur, s_cur), sh[tid]);
+  // stored r^st = r / s  =>  mu = r^T (z_s - H) r = s^2 (r^st)^T (z_pass - H) r^st
+  // + (z_s - z_pass) (r, r) (unconjugated bilinear forms; cs.rho holds the true (r, r);
+  // the second term is zero unless the seed switched in the control step beside the pass)
+  const double2 mu = cadd(cmul(cmul(s_cur, s_cur), sh[tid]),
+                          cmul(csub(cs.zs, cs.zs_mu), cs.rho));
+  cs.zs_mu = cs.zs;  // for the next mu pass
   const double2 denom = csub(mu, cmul(cdiv(cs.beta_prev, cs.alpha_prev), cs.rho));
   const double2 alpha = cdiv(cs.rho, denom);
   const double2 cc = cdiv(cmul(cs.beta_prev, alpha), cs.alpha_prev);
@@ -969,29 +1033,6 @@ __global__ __launch_bounds__(WG) void k_alpha(const AlphaArgs* __restrict__ regs
   cs.ap = cmul(mk(-cc.x, -cc.y), s_prev);
 }
 
-// ------------------------------------------------------------------ column control
-struct ControlArgs {
-  gptr<const double2> part_rho;  // [nb][nwg][B]
-  gptr<const double> part_nu;    // [nb][nwg][B]
-  int nwg;
-  gptr<ColState> cols;
-  gptr<ShiftState> sh;           // [nb][K][B]
-  gptr<ShiftCoef> coef;          // [nb][K][B]
-  gptr<const double2> z;         // [nb][K][B] energies per column
-  int K;
-  gptr<int32_t> list;            // [2][nb][K]
-  gptr<int32_t> cnt;             // [2][nb]
-  gptr<int32_t> k5cnt;           // [nb] entries for k_shift this iteration
-  gptr<int32_t> blk_active;      // [nb]
-  gptr<int32_t> blk_iter;        // [nb]
-  int nb;                   // column blocks
-  double tol;
-  int64_t max_iter;
-  int seed_switch;
-  int stall;                // > 0 (complex64 recurrences): freeze a pair whose est is
-                            // below 1e-2 and has not halved in max(stall, n/2) iterations
-  double floor_est;         // complex64 recurrences: freeze at est <= max(tol, floor_est)
-};
 
 // One workgroup per column block (B columns x K shifts):
 //   beta_n = rho_{n+1} / rho_n                                            (Eq. A6)
@@ -1006,34 +1047,48 @@ struct ControlArgs {
 // ([K][B] each) between the phases; the compaction uses wave ballots.
 constexpr int CT = 1024;  // threads of the control kernel
 
-template <int B>
-__global__ __launch_bounds__(CT) void k_control(const ControlArgs* __restrict__ regs,
-                                                 const int32_t* __restrict__ off, int nreg,
-                                                 int par) {
-  constexpr int PL = CT / B;
-  constexpr int NWAVE = CT / 64;
-  const int rg = region_of(off, nreg, blockIdx.x);
-  const ControlArgs a = regs[rg];
+// the reduction and per-column arrays of one control workgroup of CTH threads
+template <int B, int CTH>
+struct CtlShared {
+  double2 sh_rho[CTH];
+  double sh_nu[CTH];
+  int s_k[CTH];
+  double2 s_alpha[B], s_beta[B], s_c[B], s_zs[B], s_fn[B], s_fc[B], s_rhon[B];
+  double s_nrm[B], s_tol[B];
+  int s_live[B], s_sw[B];
+  int s_wsum[CTH / 64];
+  int s_any_sw;
+};
+
+// One column block's control step of iteration n: par = n mod 2 selects the Krylov
+// buffers and the halves of the coefficients and update counts, lsel = n mod 3 the
+// active list it reads (it writes list (n + 1) mod 3).  pim, act: [K][B] scratch of
+// this block (LDS in k_control, global inside the mu launch).  Every thread of the
+// workgroup calls it (it holds barriers).
+template <int B, int CTH>
+__device__ __forceinline__ void control_body(const ControlArgs& a, int cb, int par, int lsel,
+                                             CtlShared<B, CTH>& sm, double* pim,
+                                             unsigned char* act) {
+  constexpr int PL = CTH / B;
+  constexpr int NWAVE = CTH / 64;
   const int buf_new = par ^ 1;  // Krylov buffer holding r_{n+1}
-  const int tid = threadIdx.x, c = tid % B, ln = tid / B, cb = blockIdx.x - off[rg];
+  const int tid = threadIdx.x, c = tid % B, ln = tid / B;
+  const int nb = a.nb;
+  const int lnx = lsel == 2 ? 0 : lsel + 1;  // the list of iteration n + 1
   if (!a.blk_active[cb]) {
-    if (tid == 0) a.k5cnt[cb] = 0;
+    if (tid == 0) a.k5cnt[par * nb + cb] = 0;
     return;
   }
   const int K = a.K;
   const int n = a.blk_iter[cb];
-  extern __shared__ __align__(16) char dyn[];
-  double* pim = reinterpret_cast<double*>(dyn);                     // [K][B] |pi_{n+1}|
-  unsigned char* act = reinterpret_cast<unsigned char*>(dyn + (size_t)K * B * sizeof(double));
-  __shared__ double2 sh_rho[CT];
-  __shared__ double sh_nu[CT];
-  __shared__ int s_k[CT];
-  __shared__ double2 s_alpha[B], s_beta[B], s_c[B], s_zs[B], s_fn[B], s_fc[B];
-  __shared__ double s_nrm[B], s_tol[B];
-  __shared__ int s_live[B], s_sw[B];
-  __shared__ int s_wsum[NWAVE];
-  __shared__ double2 s_rhon[B];
-  __shared__ int s_any_sw;
+  double2* sh_rho = sm.sh_rho;
+  double* sh_nu = sm.sh_nu;
+  int* s_k = sm.s_k;
+  double2 *s_alpha = sm.s_alpha, *s_beta = sm.s_beta, *s_c = sm.s_c, *s_zs = sm.s_zs,
+          *s_fn = sm.s_fn, *s_fc = sm.s_fc, *s_rhon = sm.s_rhon;
+  double *s_nrm = sm.s_nrm, *s_tol = sm.s_tol;
+  int *s_live = sm.s_live, *s_sw = sm.s_sw, *s_wsum = sm.s_wsum;
+  int& s_any_sw = sm.s_any_sw;
 
   // 1. reduce rho_{n+1} and ||r_{n+1}||^2 partials
   {
@@ -1074,9 +1129,9 @@ __global__ __launch_bounds__(CT) void k_control(const ControlArgs* __restrict__ 
   __syncthreads();
 
   // 2. per (active shift, column): pi recurrence, shift coefficients, convergence
-  const int32_t* lcur = a.list + ((int64_t)par * a.nb + cb) * K;
-  int32_t* lnext = a.list + ((int64_t)(par ^ 1) * a.nb + cb) * K;
-  const int ncur = a.cnt[par * a.nb + cb];
+  const int32_t* lcur = a.list + ((int64_t)lsel * nb + cb) * K;
+  int32_t* lnext = a.list + ((int64_t)lnx * nb + cb) * K;
+  const int ncur = a.cnt[lsel * nb + cb];
   const bool live_c = s_live[c];
   const bool brk_c = a.cols[cb * B + c].breakdown;
   for (int e = ln; e < ncur; e += PL) {
@@ -1132,7 +1187,7 @@ __global__ __launch_bounds__(CT) void k_control(const ControlArgs* __restrict__ 
       st.iters = n;
       a.sh[o] = st;
     }
-    a.coef[o] = cf;
+    a.coef[(int64_t)par * nb * K * B + o] = cf;
     act[k * B + c] = (unsigned char)st.active;
     pim[k * B + c] = cabsd(st.pi);
   }
@@ -1142,7 +1197,7 @@ __global__ __launch_bounds__(CT) void k_control(const ControlArgs* __restrict__ 
   //    rank inside each wave by ballot, wave offsets by a serial prefix over waves
   const int lane = tid & 63, wave = tid >> 6;
   int base = 0;
-  for (int e0 = 0; e0 < ncur; e0 += CT) {
+  for (int e0 = 0; e0 < ncur; e0 += CTH) {
     const int e = e0 + tid;
     int keep = 0, k = -1;
     if (e < ncur) {
@@ -1267,9 +1322,22 @@ __global__ __launch_bounds__(CT) void k_control(const ControlArgs* __restrict__ 
     for (int cc = 0; cc < B; ++cc) any |= !a.cols[cb * B + cc].done;
     a.blk_active[cb] = any;
     a.blk_iter[cb] = n + 1;
-    a.k5cnt[cb] = ncur;
-    a.cnt[(par ^ 1) * a.nb + cb] = any ? nnext : 0;
+    a.k5cnt[par * nb + cb] = ncur;
+    a.cnt[lnx * nb + cb] = any ? nnext : 0;
   }
+}
+
+template <int B>
+__global__ __launch_bounds__(CT) void k_control(const ControlArgs* __restrict__ regs,
+                                                 const int32_t* __restrict__ off, int nreg,
+                                                 int par, int lsel) {
+  const int rg = region_of(off, nreg, blockIdx.x);
+  const ControlArgs a = regs[rg];
+  __shared__ CtlShared<B, CT> sm;
+  extern __shared__ __align__(16) char dyn[];
+  double* pim = reinterpret_cast<double*>(dyn);  // [K][B] |pi_{n+1}|
+  unsigned char* act = reinterpret_cast<unsigned char*>(dyn + (size_t)a.K * B * sizeof(double));
+  control_body<B, CT>(a, blockIdx.x - off[rg], par, lsel, sm, pim, act);
 }
 
 // ------------------------------------------------------------------ shift vectors (Eqs. A11-A12)
@@ -1342,23 +1410,26 @@ __device__ __forceinline__ void shift_loop(const ShiftArgs<T>& a, const int32_t*
 
 // x^(k) += alpha^(k) p^(k);  p^(k) = r_{n+1}[S] / pi^(k)_{n+1} + beta^(k) p^(k)  (Eqs. A11-A12)
 // for workgroup lb of one region (NTH threads): gx * gy * nb workgroups, NTH rows of S
-// x kch list entries x column block.  par: parity of the iteration being completed.
-// smem: at least SHIFT_KCH_MAX * B * sizeof(ShiftCoef) bytes; every thread of the
-// workgroup must call this (it holds a barrier).
+// x kch list entries x column block.  The update of iteration m: par = m mod 2 (its
+// Krylov buffer parity and the halves of its coefficients and counts), lsel = m mod 3
+// (its active list).  smem: at least SHIFT_KCH_MAX * B * sizeof(ShiftCoef) bytes;
+// every thread of the workgroup must call this (it holds a barrier).
 template <typename T, int B, int NTH>
-__device__ __forceinline__ void shift_body(const ShiftArgs<T>& a, int lb, int par, char* smem) {
+__device__ __forceinline__ void shift_body(const ShiftArgs<T>& a, int lb, int par, int lsel,
+                                           char* smem) {
   using cT = typename cplx_of<T>::type;
   const int bx = lb % a.gx, by = (lb / a.gx) % a.gy, cb = lb / (a.gx * a.gy);
-  const int cnt = a.k5cnt[cb];
+  const int cnt = a.k5cnt[par * a.nb + cb];
   const int e0 = by * a.kch;
   if (e0 >= cnt) return;  // uniform
   const int e1 = min(e0 + a.kch, cnt);
   const int K = a.K;
-  const int32_t* l = a.list + ((int64_t)par * a.nb + cb) * K;
+  const int32_t* l = a.list + ((int64_t)lsel * a.nb + cb) * K;
   // the chunk's coefficients are the same for every row: stage them once
   ShiftCoef* sc = reinterpret_cast<ShiftCoef*>(smem);
+  const ShiftCoef* cf = a.coef + (int64_t)par * a.nb * K * B;
   for (int t = threadIdx.x; t < (e1 - e0) * B; t += NTH)
-    sc[t] = a.coef[((int64_t)cb * K + l[e0 + t / B]) * B + t % B];
+    sc[t] = cf[((int64_t)cb * K + l[e0 + t / B]) * B + t % B];
   __syncthreads();
   const int64_t gid = (int64_t)bx * NTH + threadIdx.x;
   if (gid >= (int64_t)a.nS * B) return;
@@ -1380,11 +1451,11 @@ __device__ __forceinline__ void shift_body(const ShiftArgs<T>& a, int lb, int pa
 template <typename T, int B>
 __global__ __launch_bounds__(WG) void k_shift(const ShiftArgs<T>* __restrict__ regs,
                                                const int32_t* __restrict__ off, int nreg,
-                                               int par) {
+                                               int par, int lsel) {
   __shared__ __align__(16) char smem[SHIFT_KCH_MAX * B * sizeof(ShiftCoef)];
   const int rg = region_of(off, nreg, blockIdx.x);
   const ShiftArgs<T> a = regs[rg];
-  shift_body<T, B, WG>(a, blockIdx.x - off[rg], par, smem);
+  shift_body<T, B, WG>(a, blockIdx.x - off[rg], par, lsel, smem);
 }
 
 // ------------------------------------------------------------------ initialisation
@@ -1455,12 +1526,10 @@ __global__ void k_init_state(ColState* cols, ShiftState* sh, ShiftCoef* coef, do
     sh[gid] = st;
     ShiftCoef cf{};
     cf.upd = 0;
-    coef[gid] = cf;
+    coef[gid] = cf;        // both parity halves
+    coef[tot + gid] = cf;
     zcol[gid] = zpc ? zpc[cb * B + c] : z[k];
-    if (c == 0) {
-      list[(int64_t)cb * K + k] = k;
-      list[((int64_t)nb + cb) * K + k] = k;
-    }
+    if (c == 0) list[(int64_t)cb * K + k] = k;  // the list of iteration 0
   }
   if (gid < (int64_t)nb * B) {
     const int j = (int)gid;
@@ -1471,6 +1540,7 @@ __global__ void k_init_state(ColState* cols, ShiftState* sh, ShiftCoef* coef, do
     cs.alpha = mk(0, 0);
     cs.c = mk(0, 0);
     cs.zs = zpc ? zpc[j] : z[seed0];
+    cs.zs_mu = cs.zs;
     cs.scale[0] = mk(1, 0);
     cs.scale[1] = mk(1, 0);
     cs.bnorm = 1.0;
@@ -1484,7 +1554,9 @@ __global__ void k_init_state(ColState* cols, ShiftState* sh, ShiftCoef* coef, do
     const int any = cb * B < R;
     cnt[cb] = any ? K : 0;
     cnt[nb + cb] = 0;
-    k5cnt[cb] = 0;
+    cnt[2 * nb + cb] = 0;
+    k5cnt[cb] = 0;  // no x, p update is pending for iterations -2 and -1
+    k5cnt[nb + cb] = 0;
     blk_active[cb] = any;
     blk_iter[cb] = 0;
   }

@@ -194,7 +194,7 @@ struct scocg_ctx {
     int zc_mu = 0;       // z planes per workgroup of the mu pass (0: the same as g.zc)
     bool full = false;
     DevBuf r0, r1, z, cols, sh, coef, list, cnt, k5cnt, blk_active, blk_iter, rhs, srow, x, p,
-        dc, qa, part0, part1;
+        dc, qa, part0, part1, partm, pim, act;
     int32_t* h_flags = nullptr;
     ~Solve() {
       if (h_flags) (void)hipHostFree(h_flags);
@@ -513,40 +513,48 @@ struct Solver {
     return g.grid + a.nproj_wg + a.nshift_wg;
   }
 
+  // ctl, coff, nctl: control steps run by the first nctl workgroups of a MU launch
+  // (none: nctl = 0); n6 = iteration mod 6
+  struct CtlIn {
+    const ControlArgs* regs = nullptr;
+    const int32_t* off = nullptr;
+    int n = 0, n6 = 0;
+  };
+
   template <int MODE, int NF, int TX, int TY, int NT>
   static void launch_v(hipStream_t st, bool full, const StencilArgs<T>* regs, const int32_t* off,
-                       int nreg, int grid, int cur) {
+                       int nreg, int grid, int cur, CtlIn ci) {
     if (full && NF == 4)
-      hipLaunchKernelGGL((k_stencil<T, NF, B, MODE, TX, TY, NT, true>), dim3(grid), dim3(NT), 0,
-                         st, regs, off, nreg, cur);
+      hipLaunchKernelGGL((k_stencil<T, NF, B, MODE, TX, TY, NT, true>), dim3(grid + ci.n),
+                         dim3(NT), 0, st, regs, off, nreg, cur, ci.regs, ci.off, ci.n, ci.n6);
     else
-      hipLaunchKernelGGL((k_stencil<T, NF, B, MODE, TX, TY, NT, false>), dim3(grid), dim3(NT), 0,
-                         st, regs, off, nreg, cur);
+      hipLaunchKernelGGL((k_stencil<T, NF, B, MODE, TX, TY, NT, false>), dim3(grid + ci.n),
+                         dim3(NT), 0, st, regs, off, nreg, cur, ci.regs, ci.off, ci.n, ci.n6);
   }
 
   // one stencil launch over a device table of nreg regions (common nf, tile variant)
   template <int MODE>
   static void launch_table(hipStream_t st, int nf, int variant, bool full,
                            const StencilArgs<T>* regs, const int32_t* off, int nreg, int grid,
-                           int cur) {
+                           int cur, CtlIn ci = CtlIn()) {
     switch (nf) {
-      case 1: launch_v<MODE, 1, 16, 8, 1024>(st, full, regs, off, nreg, grid, cur); break;
-      case 2: launch_v<MODE, 2, 16, 8, 1024>(st, full, regs, off, nreg, grid, cur); break;
-      case 3: launch_v<MODE, 3, 16, 8, 1024>(st, full, regs, off, nreg, grid, cur); break;
+      case 1: launch_v<MODE, 1, 16, 8, 1024>(st, full, regs, off, nreg, grid, cur, ci); break;
+      case 2: launch_v<MODE, 2, 16, 8, 1024>(st, full, regs, off, nreg, grid, cur, ci); break;
+      case 3: launch_v<MODE, 3, 16, 8, 1024>(st, full, regs, off, nreg, grid, cur, ci); break;
       default:
         if constexpr (B == 8) {
           switch (variant) {
-            case 2: launch_v<MODE, 4, 16, 4, 512>(st, full, regs, off, nreg, grid, cur); break;
-            case 3: launch_v<MODE, 4, 8, 8, 512>(st, full, regs, off, nreg, grid, cur); break;
-            case 4: launch_v<MODE, 4, 16, 8, 512>(st, full, regs, off, nreg, grid, cur); break;
-            default: launch_v<MODE, 4, 16, 8, 1024>(st, full, regs, off, nreg, grid, cur); break;
+            case 2: launch_v<MODE, 4, 16, 4, 512>(st, full, regs, off, nreg, grid, cur, ci); break;
+            case 3: launch_v<MODE, 4, 8, 8, 512>(st, full, regs, off, nreg, grid, cur, ci); break;
+            case 4: launch_v<MODE, 4, 16, 8, 512>(st, full, regs, off, nreg, grid, cur, ci); break;
+            default: launch_v<MODE, 4, 16, 8, 1024>(st, full, regs, off, nreg, grid, cur, ci); break;
           }
         } else {
           switch (variant) {
-            case 2: launch_v<MODE, 4, 16, 4, 512>(st, full, regs, off, nreg, grid, cur); break;
-            case 3: launch_v<MODE, 4, 8, 8, 1024>(st, full, regs, off, nreg, grid, cur); break;
-            case 4: launch_v<MODE, 4, 8, 8, 512>(st, full, regs, off, nreg, grid, cur); break;
-            default: launch_v<MODE, 4, 16, 8, 1024>(st, full, regs, off, nreg, grid, cur); break;
+            case 2: launch_v<MODE, 4, 16, 4, 512>(st, full, regs, off, nreg, grid, cur, ci); break;
+            case 3: launch_v<MODE, 4, 8, 8, 1024>(st, full, regs, off, nreg, grid, cur, ci); break;
+            case 4: launch_v<MODE, 4, 8, 8, 512>(st, full, regs, off, nreg, grid, cur, ci); break;
+            default: launch_v<MODE, 4, 16, 8, 1024>(st, full, regs, off, nreg, grid, cur, ci); break;
           }
         }
     }
@@ -670,11 +678,13 @@ struct Solver {
     const size_t nkb = (size_t)nb * K * B;
     S.z.alloc(nkb * sizeof(double2));
     S.sh.alloc(nkb * sizeof(ShiftState));
-    S.coef.alloc(nkb * sizeof(ShiftCoef));
+    S.coef.alloc(2 * nkb * sizeof(ShiftCoef));  // by iteration parity
     S.cols.alloc((size_t)nb * B * sizeof(ColState));
-    S.list.alloc((size_t)2 * nb * K * sizeof(int32_t));
-    S.cnt.alloc((size_t)2 * nb * sizeof(int32_t));
-    S.k5cnt.alloc((size_t)nb * sizeof(int32_t));
+    S.list.alloc((size_t)3 * nb * K * sizeof(int32_t));  // iteration n: n mod 3
+    S.cnt.alloc((size_t)3 * nb * sizeof(int32_t));
+    S.k5cnt.alloc((size_t)2 * nb * sizeof(int32_t));
+    S.pim.alloc(nkb * sizeof(double));  // control scratch inside the mu launch
+    S.act.alloc(nkb);
     S.blk_active.alloc((size_t)nb * sizeof(int32_t));
     S.blk_iter.alloc((size_t)nb * sizeof(int32_t));
     const size_t xp = nkb * (size_t)S.nS;
@@ -682,8 +692,11 @@ struct Solver {
     S.p.alloc(xp * sizeof(cT));
     S.dc.alloc((size_t)std::max(h.n_atoms, 1) * nb * 4 * B * sizeof(cT));
     S.qa.alloc((size_t)std::max(h.n_atoms, 1) * nb * B * sizeof(double2));
-    S.part0.alloc((size_t)nb * std::max(S.nwg, mu_grid().nwg) * B * sizeof(double2));
+    // rho / ||r||^2 partials of the r_{n+1} pass, and the mu pass's own (the control
+    // step of n - 1 reads the former while the mu pass of n writes the latter)
+    S.part0.alloc((size_t)nb * S.nwg * B * sizeof(double2));
     S.part1.alloc((size_t)nb * S.nwg * B * sizeof(double));
+    S.partm.alloc((size_t)nb * mu_grid().nwg * B * sizeof(double2));
     if (!S.h_flags) HIPCHK(hipHostMalloc((void**)&S.h_flags, sizeof(int32_t) * 65536));
   }
 
@@ -764,9 +777,9 @@ struct Solver {
   void fit_partials() {
     const size_t need = (size_t)S.nb * S.g.nwg * B;
     const size_t need_mu = (size_t)S.nb * mu_grid().nwg * B;
-    const size_t n0 = std::max(need, need_mu);
-    if (S.part0.bytes < n0 * sizeof(double2)) S.part0.alloc(n0 * sizeof(double2));
+    if (S.part0.bytes < need * sizeof(double2)) S.part0.alloc(need * sizeof(double2));
     if (S.part1.bytes < need * sizeof(double)) S.part1.alloc(need * sizeof(double));
+    if (S.partm.bytes < need_mu * sizeof(double2)) S.partm.alloc(need_mu * sizeof(double2));
   }
 
   // Device time per seed iteration of `iters` iterations from the initial state
@@ -888,6 +901,9 @@ struct Solver {
     S.r1.release();
     S.part0.release();
     S.part1.release();
+    S.partm.release();
+    S.pim.release();
+    S.act.release();
     S.dc.release();
     S.qa.release();
   }
@@ -1240,8 +1256,9 @@ struct Batch {
       int32_t* act = S.blk_active.template as<int32_t>();
       double2* part0 = S.part0.template as<double2>();
       double* part1 = S.part1.template as<double>();
+      double2* partm = S.partm.template as<double2>();
       const StencilGrid gm = p->mu_grid();
-      StencilArgs<T> m = p->stencil_args(MODE_MU, gm, S.nb, cols, act, part0, nullptr,
+      StencilArgs<T> m = p->stencil_args(MODE_MU, gm, S.nb, cols, act, partm, nullptr,
                                          S.dc.template as<cT>(), S.qa.template as<double2>());
       // x, p update of iteration n inside the mu launch of iteration n + 1
       m.shift = p->shift_args(SV::tile_cfg(h.nf == 4 ? variant : 1).nt, kch);
@@ -1259,7 +1276,7 @@ struct Batch {
       up.push_back(u);
       oup.push_back(oup.back() + SV::stencil_wgs(u, S.g));
       AlphaArgs aa{};
-      aa.part = to_g(part0);
+      aa.part = to_g(partm);
       aa.nwg = gm.nwg;
       aa.qa = to_g(S.qa.template as<double2>());
       aa.n_atoms = h.n_atoms;
@@ -1279,6 +1296,8 @@ struct Batch {
       ca.list = to_g(S.list.template as<int32_t>());
       ca.cnt = to_g(S.cnt.template as<int32_t>());
       ca.k5cnt = to_g(S.k5cnt.template as<int32_t>());
+      ca.pim = to_g(S.pim.template as<double>());
+      ca.act = to_g(S.act.template as<unsigned char>());
       ca.blk_active = to_g(act);
       ca.blk_iter = to_g(S.blk_iter.template as<int32_t>());
       ca.nb = S.nb;
@@ -1321,10 +1340,23 @@ struct Batch {
     HIPCHK(hipEventRecord(ev[2 * fam + end], st));
   }
 
-  void one_iteration(int par, hipEvent_t* ev) {
+  // Iteration s2 of a poll chunk of `poll` iterations (poll is a multiple of 6, so s2
+  // mod 6 is the absolute iteration n mod 6): the mu launch of n also runs the control
+  // step of n - 1 (except at the start of a chunk, whose previous control step ended
+  // the last chunk) and the x, p update of n - 2; the chunk's last iteration runs its
+  // control step alone, so that the host poll after the chunk sees it.
+  void one_iteration(int s2, int poll, hipEvent_t* ev) {
+    const int par = s2 & 1, n6 = s2 % 6;
+    typename SV::CtlIn ci;
+    if (s2 > 0) {
+      ci.regs = t_ctl.as<ControlArgs>();
+      ci.off = o_blk.as<int32_t>();
+      ci.n = g_blk;
+      ci.n6 = n6;
+    }
     mark(ev, SCOCG_K_MU, 0);
     SV::template launch_table<MODE_MU>(st, nf, variant, full, t_mu.as<StencilArgs<T>>(),
-                                       o_mu.as<int32_t>(), n(), g_mu, par);
+                                       o_mu.as<int32_t>(), n(), g_mu, par, ci);
     mark(ev, SCOCG_K_MU, 1);
     mark(ev, SCOCG_K_ALPHA, 0);
     hipLaunchKernelGGL((k_alpha<B>), dim3(g_blk), dim3(WG), 0, st, t_alpha.as<AlphaArgs>(),
@@ -1335,18 +1367,19 @@ struct Batch {
     SV::template launch_table<MODE_UPDATE>(st, nf, variant, full, t_upd.as<StencilArgs<T>>(),
                                            o_upd.as<int32_t>(), n(), g_upd, par);
     mark(ev, SCOCG_K_UPDATE, 1);
-    mark(ev, SCOCG_K_CONTROL, 0);
-    hipLaunchKernelGGL((k_control<B>), dim3(g_blk), dim3(CT), ctl_lds, st,
-                       t_ctl.as<ControlArgs>(), o_blk.as<int32_t>(), n(), par);
-    KCHK();
-    mark(ev, SCOCG_K_CONTROL, 1);
-    // the x, p update of this iteration runs in the next mu launch (or the flush)
+    if (s2 == poll - 1) {
+      mark(ev, SCOCG_K_CONTROL, 0);
+      hipLaunchKernelGGL((k_control<B>), dim3(g_blk), dim3(CT), ctl_lds, st,
+                         t_ctl.as<ControlArgs>(), o_blk.as<int32_t>(), n(), par, n6 % 3);
+      KCHK();
+      mark(ev, SCOCG_K_CONTROL, 1);
+    }
   }
 
-  // x, p update of the last iteration run (parity par)
-  void flush_shift(int par) {
+  // x, p update of iteration m (parity m mod 2, list m mod 3) outside the mu launches
+  void flush_shift(int par, int lsel) {
     hipLaunchKernelGGL((k_shift<T, B>), dim3(g_shift), dim3(WG), 0, st,
-                       t_shift.as<ShiftArgs<T>>(), o_shift.as<int32_t>(), n(), par);
+                       t_shift.as<ShiftArgs<T>>(), o_shift.as<int32_t>(), n(), par, lsel);
     KCHK();
   }
 
@@ -1356,7 +1389,9 @@ struct Batch {
   int64_t iterate(const scocg_solve_opts& o, double* kms, int64_t* kcount, hipEvent_t t0,
                   double* region_ms) {
     int poll = o.poll_every > 0 ? o.poll_every : 16;
-    if (poll & 1) ++poll;  // even: the buffer and list parities return to 0 after each poll
+    // a multiple of 6: the buffer parity (2) and the list index (3) repeat per chunk,
+    // so one captured chunk serves every chunk
+    poll = (poll + 5) / 6 * 6;
     int64_t it = 0;
     Graph graph;
     // timing: one event pair per kernel family per iteration of a poll chunk
@@ -1377,7 +1412,7 @@ struct Batch {
         if (!graph.x) {
           HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
           try {
-            for (int s2 = 0; s2 < poll; ++s2) one_iteration(s2 & 1, ev_of(s2));
+            for (int s2 = 0; s2 < poll; ++s2) one_iteration(s2, poll, ev_of(s2));
           } catch (...) {
             // leave the stream usable: end the capture and drop the partial graph
             hipGraph_t partial = nullptr;
@@ -1390,7 +1425,7 @@ struct Batch {
         }
         HIPCHK(hipGraphLaunch(graph.x, st));
       } else {
-        for (int s2 = 0; s2 < poll; ++s2) one_iteration(s2 & 1, ev_of(s2));
+        for (int s2 = 0; s2 < poll; ++s2) one_iteration(s2, poll, ev_of(s2));
       }
       it += poll;
       if (evp) HIPCHK(hipEventRecord(*evp, st));
@@ -1401,8 +1436,10 @@ struct Batch {
       if (o.timing) {
         for (int s2 = 0; s2 < poll; ++s2)
           for (int f = 0; f < SCOCG_K_FAMILIES; ++f) {
-            // the projector contraction and the x, p update run inside the MU launch
+            // the projector contraction, the x, p update and (but at the end of a
+            // chunk) the control step run inside the MU launch
             if (f == SCOCG_K_PROJ || f == SCOCG_K_SHIFT) continue;
+            if (f == SCOCG_K_CONTROL && s2 != poll - 1) continue;
             if (o.timing == 2 && f != SCOCG_K_UPDATE) continue;
             float t = 0.f;
             hipEvent_t* e = ev_of(s2);
@@ -1433,8 +1470,10 @@ struct Batch {
       }
       if (!any_all || it >= o.max_iter + poll) break;
     }
-    // every poll chunk ends with an odd-parity iteration (poll is even)
-    flush_shift(1);
+    // the x, p updates of the last two iterations (it is a multiple of 6): iteration
+    // it - 2 has parity 0 and list 1, it - 1 parity 1 and list 2
+    flush_shift(0, 1);
+    flush_shift(1, 2);
     return it;
   }
 };
