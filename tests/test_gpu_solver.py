@@ -334,6 +334,65 @@ def test_max_iter_cut_off_reports_status(dev):
     h.destroy()
 
 
+@pytest.mark.parametrize("m", [1, 2, 3, 5, 7, 13, 19, 37])
+def test_truncated_solve_matches_the_oracle_after_the_same_iterations(dev, m):
+    """A solve cut off after m seed iterations returns x^{(k)}_m of Eqs. A11-A12 for every
+    energy: the x, p update of iteration n runs inside the mu launch of n + 2 and the
+    last two are flushed at the end, whatever m is modulo the list rotation (3), the
+    coefficient parity (2) and the poll chunk; direct launches and graph replays of
+    two chunk lengths give the same bits."""
+    p = small(8, 8, 12, 4, True, K=5, nb=2, nt=1)
+    h = scocg.create_from_problem(p, precision=scocg.FP64)
+    outs = []
+    for g, poll in ((False, 6), (True, 12), (True, 18)):
+        rc, rep = h.solve(p.z, p.rhs_idx, tol=1e-30, max_iter=m, init_seed=2, full=True,
+                          use_graph=g, poll_every=poll)
+        assert rc == scocg.NOT_ALL_CONVERGED
+        assert (rep["status"] == scocg.PAIR_MAXITER).all() and (rep["iters"] == m).all()
+        outs.append(h.green_columns())
+    h.destroy()
+    for G in outs[1:]:
+        assert np.array_equal(G, outs[0])
+    G = outs[0]
+    for j, col in enumerate(p.rhs_idx):
+        b = np.zeros(p.n, np.complex128)
+        b[col] = 1.0
+        ref = oracle.shifted_cocg(p, p.z, b, seed0=2, tol=1e-30, max_iter=m)
+        assert (ref["iters"] == m).all()
+        rel = np.linalg.norm(G[:, j] - ref["x"], axis=1) / np.linalg.norm(ref["x"], axis=1)
+        assert rel.max() <= 1e-11, (j, rel)
+
+
+def test_truncated_solve_around_a_seed_switch_matches_the_oracle(dev):
+    """The seed (below the spectrum) freezes first and hands the recurrence to another
+    energy (Eq. A13); solves cut off at the freeze iteration and just after it, where the
+    mu pass still ran with the old seed energy, match the oracle's truncated shifted
+    COCG pair by pair (same freeze iterations, same x)."""
+    p = small(8, 8, 12, 4, True, K=5, nb=2, nt=1)
+    p = p.with_(z=np.array([-4.0, -0.3, 0.2, 0.9, 1.7]) + 1e-3j)
+    tol = 1e-9
+    h = scocg.create_from_problem(p, precision=scocg.FP64)
+    rc, rep = h.solve(p.z, p.rhs_idx, tol=tol, init_seed=0, full=True)
+    assert rc == scocg.OK
+    fj = rep["iters"][0].copy()  # the seed's freeze iteration per column
+    f = int(fj.max())
+    assert f + 8 < rep["iters"][1:].min()
+    for m in (f, f + 1, f + 2, f + 3, f + 8):
+        rc, rep = h.solve(p.z, p.rhs_idx, tol=tol, max_iter=m, init_seed=0, full=True,
+                          poll_every=6)
+        # no switch at the cut-off iteration itself: no iteration follows it
+        assert rc == scocg.NOT_ALL_CONVERGED and rep["n_switches"] == int((fj < m).sum())
+        G = h.green_columns()
+        for j, col in enumerate(p.rhs_idx):
+            b = np.zeros(p.n, np.complex128)
+            b[col] = 1.0
+            ref = oracle.shifted_cocg(p, p.z, b, seed0=0, tol=tol, max_iter=m)
+            assert np.array_equal(rep["iters"][:, j], ref["iters"]), (m, j)
+            rel = np.linalg.norm(G[:, j] - ref["x"], axis=1) / np.linalg.norm(ref["x"], axis=1)
+            assert rel.max() <= 1e-11, (m, j, rel)
+    h.destroy()
+
+
 def test_invalid_solve_arguments(dev):
     p = small(6, 6, 8, 4, False)
     h = scocg.create_from_problem(p, precision=scocg.FP64)
