@@ -85,23 +85,37 @@ def kernel_source_hash():
     return d.hexdigest()[:16]
 
 
-def measured_traffic(workload, precision, tile, zchunk, cache_mode=0):
-    """HBM bytes per launch of the r_{n+1} pass from the committed counter summary
-    (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's readings); None when the
-    summary is missing, covers another workload or launch shape, or the device code
-    changed since."""
+def traffic_records():
+    """The records of the committed counter summary: one per measured launch shape,
+    each opened by its 'workload:' line."""
+    recs = []
     try:
         with open(TRAFFIC_FILE) as fh:
-            kv = dict(l.split(":", 1) for l in fh if ":" in l and not l.startswith("#"))
+            for line in fh:
+                if line.startswith("#") or ":" not in line:
+                    continue
+                k, v = (s.strip() for s in line.split(":", 1))
+                if k == "workload":
+                    recs.append({})
+                if recs:
+                    recs[-1][k] = v
     except OSError:
-        return None, None
-    kv = {k.strip(): v.strip() for k, v in kv.items()}
-    if (kv.get("workload") != workload or kv.get("precision") != precision
-            or kv.get("tile") != str(tile) or kv.get("zchunk") != str(zchunk)
-            or kv.get("cache_mode", "0") != str(cache_mode)
-            or kv.get("kernel_source_sha256_16") != kernel_source_hash()):
-        return None, None
-    return float(kv["traffic_bytes_per_launch"]), float(kv["algorithmic_bytes_per_launch"])
+        pass
+    return recs
+
+
+def measured_traffic(workload, precision, tile, zchunk, cache_mode=0):
+    """HBM-side bytes per launch of the r_{n+1} pass from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's readings); None when no record
+    covers this workload and launch shape, or the device code changed since."""
+    for kv in traffic_records():
+        if (kv.get("workload") == workload and kv.get("precision") == precision
+                and kv.get("tile") == str(tile) and kv.get("zchunk") == str(zchunk)
+                and kv.get("cache_mode", "0") == str(cache_mode)
+                and kv.get("kernel_source_sha256_16") == kernel_source_hash()):
+            return (float(kv["traffic_bytes_per_launch"]),
+                    float(kv["algorithmic_bytes_per_launch"]))
+    return None, None
 
 
 def cpu_baseline(p, n_energies, n_cols, iters_cap, tol, mean_iters):

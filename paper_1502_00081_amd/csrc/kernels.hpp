@@ -501,8 +501,13 @@ struct StencilWG {
   static constexpr int PL = NT / B;  // point lanes
   static_assert(NT % B == 0 && (TX * TY) % PL == 0, "tile must split evenly over point lanes");
   static constexpr int OPT = TX * TY / PL;  // owned points per thread per plane
-  static constexpr int RING = PX * PY - TX * TY;
+  // halo ring of the cross-shaped stencil: the bands above and below the interior
+  // rows over the interior columns only, then the side pieces of the interior rows
+  // (the tile corners are never read, so they are never loaded)
+  static constexpr int BAND = (PY - TY) * TX;
+  static constexpr int RING = BAND + TY * (PX - TX);
   static constexpr int HPT = (RING + PL - 1) / PL;  // halo slots per thread
+  static_assert(RING % 8 == 0, "idle halo slots must fill whole waves");
   // one spare slot per column absorbs the writes of unused halo lanes
   static constexpr int TILE_BYTES = (PX * PY + 1) * B * (int)sizeof(cT);
   static constexpr int RED_BYTES = NT * (int)(sizeof(double2) + sizeof(double));
@@ -524,6 +529,7 @@ struct StencilWG {
   uint32_t pstride;   // bytes per plane
   uint32_t qoff[OPT], hoff[HPT];  // lane byte offsets inside a plane
   int iofs[OPT], hl[HPT], gq[OPT];
+  int nh;  // halo slots of this lane that hold ring points (the rest stay idle)
   bool val[OPT];
   cT Q[OPT][W];
   cT pq[OPT], ph[HPT], pp[OPT];
@@ -565,18 +571,21 @@ struct StencilWG {
       gq[m] = wrapi(gy, ny) * nx + wrapi(gx, nx);
       qoff[m] = ((uint32_t)gq[m] * B + c) * ESZ;
     }
-    // halo slots: full-width bands above and below the interior rows, then the
-    // side pieces of the interior rows; unused lanes write the spare slot
+    // halo slots h = pl + i * PL: the interior-width bands above and below the
+    // interior rows, then the side pieces of the interior rows; slots past the ring
+    // (i >= nh; whole waves, as RING is a multiple of the 8 point lanes of a wave)
+    // neither load nor store
+    nh = pl < RING ? (RING - 1 - pl) / PL + 1 : 0;
 #pragma unroll
     for (int i = 0; i < HPT; ++i) {
       const int h = pl + i * PL;
-      int sx = 0, sy = 0;
-      if (h < (PY - TY) * PX) {
-        const int rr = h / PX;
+      int sx = O, sy = 0;
+      if (h < BAND) {
+        const int rr = h / TX;
         sy = rr < O ? rr : rr + TY;
-        sx = h % PX;
+        sx = O + h % TX;
       } else if (h < RING) {
-        const int q = h - (PY - TY) * PX;
+        const int q = h - BAND;
         sy = O + q / (PX - TX);
         const int s2 = q % (PX - TX);
         sx = s2 < O ? s2 : s2 + TX;
@@ -644,7 +653,8 @@ struct StencilWG {
                     : *reinterpret_cast<const cT*>(iobase + pc * pstride + qoff[m]);
     }
 #pragma unroll
-    for (int i = 0; i < HPT; ++i) ph[i] = ldr(pc, hoff[i]);
+    for (int i = 0; i < HPT; ++i)
+      if (i < nh) ph[i] = ldr(pc, hoff[i]);
   }
 
   // one (virtual) plane with queue rotation S: logical queue index d (plane
@@ -684,7 +694,8 @@ struct StencilWG {
       if (MODE == MODE_UPDATE) cp[m] = pp[m];
     }
 #pragma unroll
-    for (int i = 0; i < HPT; ++i) lds[hl[i]] = ph[i];
+    for (int i = 0; i < HPT; ++i)
+      if (i < nh) lds[hl[i]] = ph[i];
     // readers of this buffer (plane iz-2) passed the previous plane's barrier
     // before these writes, so one barrier per plane suffices
     __syncthreads();
@@ -880,6 +891,9 @@ template <int B, int CTH>
 __device__ __forceinline__ void control_body(const ControlArgs& a, int cb, int par, int lsel,
                                              CtlShared<B, CTH>& sm, double* pim,
                                              unsigned char* act);
+template <typename T, int B, int NTH>
+__device__ __forceinline__ void shift_body(const ShiftArgs<T>& a, int lb, int par, int lsel,
+                                           char* smem);
 
 // Stencil pass kernel.  MODE_MU launches additionally carry the projector
 // contraction of r_n: the first nproj_wg workgroups (a multiple of 8, so the

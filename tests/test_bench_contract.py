@@ -10,27 +10,28 @@ import bench
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def _summary_fields():
-    with open(bench.TRAFFIC_FILE) as fh:
-        kv = dict(l.split(":", 1) for l in fh if ":" in l and not l.startswith("#"))
-    return {k.strip(): v.strip() for k, v in kv.items()}
-
-
 def test_traffic_summary_matches_current_device_code():
     """Any change to the stencil kernels must come with a fresh counter summary; the
-    bench reports traffic only for the workload, precision and launch shape it names."""
-    kv = _summary_fields()
-    wl, prec, tile, zc = kv["workload"], kv["precision"], int(kv["tile"]), int(kv["zchunk"])
-    traffic, alg = bench.measured_traffic(wl, prec, tile, zc)
-    assert traffic is not None, ("profiles/ traffic summary is stale: re-run the FETCH_SIZE / "
-                                 "WRITE_SIZE passes for the current kernels.hpp")
-    assert wl == "medium_48x48x96" and prec == "fp64"
-    assert alg == 3 * 221184 * 16 * 64  # every column block active in the counted launches
-    assert 1.0 <= traffic / alg < 2.0
-    # another shape or workload gets no traffic figure
-    assert bench.measured_traffic(wl, prec, tile % 4 + 1, zc) == (None, None)
-    assert bench.measured_traffic(wl, prec, tile, zc + 1) == (None, None)
-    assert bench.measured_traffic("tiny_16x16x24", prec, tile, zc) == (None, None)
+    bench reports traffic only for the workload, precision and launch shapes it names
+    (one record per shape the autotuner picks on the medium workload)."""
+    recs = bench.traffic_records()
+    assert len(recs) >= 1
+    shapes = {(int(kv["tile"]), int(kv["zchunk"]), int(kv.get("cache_mode", 0))) for kv in recs}
+    assert len(shapes) == len(recs)  # no shape twice
+    for kv in recs:
+        wl, prec, tile, zc = kv["workload"], kv["precision"], int(kv["tile"]), int(kv["zchunk"])
+        cm = int(kv.get("cache_mode", 0))
+        traffic, alg = bench.measured_traffic(wl, prec, tile, zc, cm)
+        assert traffic is not None, ("profiles/ traffic summary is stale: re-run the "
+                                     "FETCH_SIZE / WRITE_SIZE passes for the current kernels.hpp")
+        assert wl == "medium_48x48x96" and prec == "fp64"
+        assert alg == 3 * 221184 * 16 * 64  # every column block active in the counted launches
+        assert 1.0 <= traffic / alg < 2.0
+        # another shape or workload gets no traffic figure
+        for other in ((tile % 4 + 1, zc, cm), (tile, zc + 1, cm), (tile, zc, (cm + 1) % 3)):
+            if other not in shapes:
+                assert bench.measured_traffic(wl, prec, *other) == (None, None)
+        assert bench.measured_traffic("tiny_16x16x24", prec, tile, zc, cm) == (None, None)
 
 
 def test_more_than_one_gpu_is_refused():
