@@ -39,3 +39,28 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, cwd=ROOT)
     assert r.returncode == 2
     assert "one GPU only" in r.stderr
+
+
+def test_recorded_tuning_is_in_the_library_format_and_has_a_traffic_record():
+    """The bench's recorded launch shape for the medium workload is a line the library
+    reads (its exact record form, values in range), and the counter summary covers it."""
+    import json
+    import re
+    with open(bench.TUNE_RECORDS) as fh:
+        lines = [l.rstrip("\n") for l in fh if l.strip()]
+    form = re.compile(
+        r'\{"arch": "gfx\w+", "precision": "(fp64|mixed)", "grid": \[\d+, \d+, \d+\], '
+        r'"nf": \d, "atoms": \d+, "block_width": \d+, "blocks": \d+, "energies": \d+, '
+        r'"rows": \d+, "tile": [1-4], "zchunk": \d+, "shift_chunk": (1|4|16), '
+        r'"cache_mode": [0-2], "zchunk_mu": \d+\}$')
+    assert lines and all(form.match(l) for l in lines)
+    recs = [json.loads(l) for l in lines]
+    med = [r for r in recs if r["grid"] == [48, 48, 96] and r["precision"] == "fp64"]
+    assert len(med) == 1
+    r = med[0]
+    assert (r["nf"], r["atoms"], r["block_width"], r["blocks"], r["energies"], r["rows"]) == \
+        (4, 40, 8, 8, 128, 64)
+    assert 1 <= r["zchunk"] <= 96 and 0 <= r["zchunk_mu"] <= 96
+    traffic, _ = bench.measured_traffic("medium_48x48x96", "fp64", r["tile"], r["zchunk"],
+                                        r["cache_mode"])
+    assert traffic is not None
