@@ -91,10 +91,12 @@ def use_tune_records(a):
         return None
     import shutil
     import tempfile
+    import atexit
     fd, path = tempfile.mkstemp(prefix="scocg_tune_", suffix=".jsonl")
     os.close(fd)
     shutil.copyfile(TUNE_RECORDS, path)
     os.environ["SCOCG_TUNE_CACHE"] = path
+    atexit.register(lambda: os.path.exists(path) and os.remove(path))
     return path
 KERNEL_SOURCES = ("paper_1502_00081_amd/csrc/kernels.hpp",)  # the device code
 
