@@ -7,18 +7,22 @@
 //   shift vectors x, p  [nb][K][nS][B]    x complex128, p complex<T>
 //   shift state         [nb][K][B]        ShiftState (pi_{n-1}, pi_n, status)
 //   column state        [nb*B]            ColState (seed scalars, FP64)
-// Per seed iteration n the host enqueues:
-//   k_stencil<MU>     partials of mu_n = (r_n, A r_n),  A = z_s - H    (Eq. A5), plus, in
-//                     extra workgroups, the projector contraction C_a = P_a^T r_n
+// Per seed iteration n the host enqueues three launches:
+//   k_stencil<MU>     partials of mu_n = (r_n, A r_n),  A = z_s - H    (Eq. A5); in extra
+//                     workgroups of the same launch: the projector contraction
+//                     C_a = P_a^T r_n, the control step of iteration n-1 (control_body:
+//                     beta (Eq. A6); pi, alpha^(i), beta^(i) per shift (Eqs. A8-A10);
+//                     convergence, compaction of active shifts; seed switch (Eq. A13)),
+//                     and the x^(i), p^(i) update of iteration n-2 on the rows S
+//                     (Eqs. A11-A12 with Eq. A7)
 //   k_alpha     alpha_n, c_n = beta_{n-1} alpha_n / alpha_{n-1}       (Eq. A5)
 //   k_stencil<UPDATE> r_{n+1} = (1+c_n) r_n - alpha_n A r_n - c_n r_{n-1}  (Eq. A3), in place
 //                     over r_{n-1}; partials of rho_{n+1}, ||r_{n+1}||^2
-//   k_control   beta_n (Eq. A6); pi, alpha^(i), beta^(i) per shift (Eqs. A8-A10);
-//               convergence, compaction of active shifts; seed switch (Eq. A13)
-//   x^(i), p^(i) on the rows S (Eqs. A11-A12 with Eq. A7): in extra workgroups of the
-//               next iteration's k_stencil<MU> launch (k_shift after the last iteration)
-// A r_n is recomputed in the UPDATE pass instead of being stored, so one
-// iteration streams r_n twice, r_{n-1} once and writes r_{n+1} once.
+// and, at the end of each poll chunk, the control step of its last iteration alone
+// (k_control, so that the host poll sees it); after the last iteration k_shift runs
+// the two x, p updates still pending.  A r_n is recomputed in the UPDATE pass instead
+// of being stored, so one iteration streams r_n twice, r_{n-1} once and writes r_{n+1}
+// once.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -202,7 +206,7 @@ struct StencilArgs {
   gptr<double> part1;         // [nb][nwg][B] ||r||^2 partials (UPDATE)
   int nproj_wg;          // MU: leading workgroups doing the projector contraction
   ProjArgs<T> proj;
-  int nshift_wg;         // MU: next workgroups doing the previous iteration's x, p update
+  int nshift_wg;         // MU: next workgroups doing the x, p update of iteration n - 2
   ShiftArgs<T> shift;
   int cache_mode;        // UPDATE: 0 r_{n-1} loads and r_{n+1} stores nontemporal; 1 r_{n+1}
                          // stores ordinary (the next mu pass reads them); 2 both ordinary

@@ -1260,7 +1260,7 @@ struct Batch {
       const StencilGrid gm = p->mu_grid();
       StencilArgs<T> m = p->stencil_args(MODE_MU, gm, S.nb, cols, act, partm, nullptr,
                                          S.dc.template as<cT>(), S.qa.template as<double2>());
-      // x, p update of iteration n inside the mu launch of iteration n + 1
+      // x, p update of iteration n inside the mu launch of iteration n + 2
       m.shift = p->shift_args(SV::tile_cfg(h.nf == 4 ? variant : 1).nt, kch);
       m.nshift_wg = (m.shift.gx * m.shift.gy * S.nb + 7) / 8 * 8;
       StencilArgs<T> u = p->stencil_args(MODE_UPDATE, S.g, S.nb, cols, act, part0, part1,
