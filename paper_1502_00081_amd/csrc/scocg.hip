@@ -1405,7 +1405,9 @@ struct Batch {
     std::vector<char> done(sv.size(), 0);
     auto ev_of = [&](int s2) { return o.timing ? &evh[(size_t)s2 * 2 * SCOCG_K_FAMILIES] : nullptr; };
     // events recorded during capture cannot be read back after a replay on this
-    // runtime: timing runs use direct launches
+    // runtime (and an external event-record node, hipEventRecordWithFlags with
+    // hipEventRecordExternal, is refused during capture): timing runs use direct
+    // launches
     const bool use_graph = o.use_graph && !o.timing;
     while (true) {
       if (use_graph) {
