@@ -75,3 +75,34 @@ def test_out_of_range_tune_record_is_ignored(tmp_path, monkeypatch):
     assert r2["tuned"], "an out-of-range record must not be used"
     assert r2["tile"] in (1, 2, 3, 4) and r2["shift_chunk"] in (1, 4, 16)
     assert len(path.read_text().splitlines()) == 2
+
+
+def test_recorded_medium_shape_is_taken_by_the_library(tmp_path, monkeypatch):
+    """The bench's recorded MI355X shape for the medium workload (the repository's
+    tuned_shapes.jsonl) is read by the library itself: an autotuned solve of that
+    workload runs no trials and reports exactly the recorded shape."""
+    import os
+    import shutil
+    rec_file = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                            "paper_1502_00081_amd", "tuned_shapes.jsonl")
+    path = tmp_path / "tune.jsonl"
+    shutil.copyfile(rec_file, path)
+    monkeypatch.setenv("SCOCG_TUNE_CACHE", str(path))
+    rec = [json.loads(l) for l in path.read_text().splitlines() if '"grid": [48, 48, 96]' in l][0]
+    p = W.medium_fp64()
+    h = scocg.create_from_problem(p, precision=scocg.FP64)
+    try:
+        arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+        rc, rep = h.solve(p.z, p.rhs_idx, tol=1e-8, max_iter=18, tile=A, zchunk=A,
+                          shift_chunk=A, cache_mode=A, zchunk_mu=A)
+    finally:
+        h.destroy()
+    assert rc in (scocg.OK, scocg.NOT_ALL_CONVERGED)
+    if arch != rec["arch"]:
+        assert rep["tuned"]  # another architecture has no record and tunes
+        return
+    assert not rep["tuned"] and rep["tune_ms"] == 0
+    assert (rep["tile"], rep["zchunk"], rep["shift_chunk"], rep["cache_mode"],
+            rep["zchunk_mu"]) == (rec["tile"], rec["zchunk"], rec["shift_chunk"],
+                                  rec["cache_mode"], rec["zchunk_mu"])
+    assert len(path.read_text().splitlines()) == 1  # nothing appended
