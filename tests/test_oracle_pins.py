@@ -207,6 +207,23 @@ def test_shifted_cocg_equals_conventional_and_dense():
         assert true_res <= 2e-12
 
 
+def test_truncated_shifted_iterates_equal_conventional_iterates():
+    """Eqs. A7-A12: the shifted recurrence builds, for every energy, the same Krylov
+    iterates as a conventional COCG run at that energy, so after any number m of seed
+    iterations (no convergence, no switch) x^(k)_m equals the conventional x_m.  This
+    pins the meaning of a solve cut off after m iterations, which the GPU tests compare
+    against."""
+    p = small_problem(8, 8, 12, projectors=True, eta=1e-3, K=5)
+    b = unit(p.n, p.rhs_idx[0])
+    for m in (1, 2, 3, 10, 25, 40):
+        s = oracle.shifted_cocg(p, p.z, b, seed0=2, tol=0.0, max_iter=m)
+        assert (s["iters"] == m).all()
+        for k in range(p.z.size):
+            c = oracle.cocg(p, p.z[k], b, tol=0.0, max_iter=m)
+            assert c["iters"] == m
+            assert np.linalg.norm(s["x"][k] - c["x"]) <= 1e-10 * np.linalg.norm(c["x"]), (m, k)
+
+
 def test_shifted_single_shift_is_conventional():
     p = small_problem(6, 6, 10, projectors=True, eta=1e-3, K=1)
     b = unit(p.n, p.rhs_idx[0])

@@ -32,6 +32,9 @@ MUTATIONS = {
                     "r_next[i] = (1.0 + c) * r[i] - alpha * ar[i];\n        const cplx rho_next"),
     # seed switching rebases pi with the wrong index (n+1 factor for both)
     "switch_rebase": ("pi[k] /= f_cur;", "pi[k] /= f_next;"),
+    # the shift's x takes the new direction p_{n+1} instead of p_n (Eqs. A11-A12 order)
+    "x_uses_new_p": ("x_out[k * n + i] += ak * p[k * n + i];\n                p[k * n + i] = r_next[i] / pi_next[k] + bk * p[k * n + i];",
+                     "p[k * n + i] = r_next[i] / pi_next[k] + bk * p[k * n + i];\n                x_out[k * n + i] += ak * p[k * n + i];"),
 }
 
 
@@ -107,8 +110,24 @@ def _pin_collinear():
     return np.linalg.norm(rk - seed["snap"] / pi) <= 1e-7 * np.linalg.norm(rk)
 
 
+def _pin_truncated():
+    """After m seed iterations every shift's x equals the conventional COCG iterate at
+    its energy (same Krylov iterates, Eqs. A7-A12)."""
+    p = _problem()
+    b = np.zeros(p.n, complex)
+    b[p.rhs_idx[0]] = 1
+    m = 12
+    s = oracle.shifted_cocg(p, p.z, b, seed0=3, tol=0.0, max_iter=m)
+    ok = True
+    for k in (0, 5):
+        c = oracle.cocg(p, p.z[k], b, tol=0.0, max_iter=m)["x"]
+        ok &= np.linalg.norm(s["x"][k] - c) <= 1e-10 * np.linalg.norm(c)
+    return ok
+
+
 def test_pins_pass_on_the_real_oracle():
     assert _pin_apply_h() and _pin_cocg_dense() and _pin_shifted_dense() and _pin_collinear()
+    assert _pin_truncated()
 
 
 @pytest.mark.parametrize("name,pin", [
@@ -121,6 +140,7 @@ def test_pins_pass_on_the_real_oracle():
     ("sigma_sign", _pin_shifted_dense),
     ("drop_r_prev", _pin_cocg_dense),
     ("switch_rebase", _pin_shifted_dense),
+    ("x_uses_new_p", _pin_truncated),
 ])
 def test_planted_mistake_is_caught(mutated, name, pin):
     mutated(name)
